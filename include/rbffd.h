@@ -1,0 +1,145 @@
+/*
+ * rbffd.h -- C ABI of the MI355X (gfx950) RBF-FD stencil library.
+ *
+ * The library computes the data-parallel hot path of strong-form mesh-free
+ * discretisation (Slak & Kosec, "Medusa", Sec. 2.1, 2.2.2, 2.3.2):
+ *   1. stencil selection: for each node the n_i closest nodes, itself first;
+ *   2. RBF-FD weights: for each stencil the augmented polyharmonic-spline plus
+ *      monomial system of eq. (rbf-system-aug), solved for the Laplacian and
+ *      first-derivative weights;
+ *   3. the sparse operator in CSR form (at most sum n_i nonzeros).
+ *
+ * Conventions shared by every call
+ *   - All array arguments are DEVICE pointers unless stated otherwise.  The
+ *     caller allocates and owns every buffer, including the workspace; the
+ *     library never allocates on these calls.
+ *   - Indices are 0-based.  Node coordinates X are row-major [N][d] float64.
+ *   - offsets[N+1] (int64) is the exclusive prefix sum of the stencil sizes n_i;
+ *     nnz = offsets[N].  Stencil i occupies idx[offsets[i] .. offsets[i+1]).
+ *   - Weight arrays are operator-major: w[r * nnz + offsets[i] + j] is the
+ *     weight of stencil node j of node i for the r-th operator selected in
+ *     op_mask, operators ordered LAP, DX, DY, DZ.
+ *   - Every call is asynchronous on the context's HIP stream.  Argument errors
+ *     are detected on the host before any launch and returned as negative
+ *     codes; numerical trouble is never a call failure but a per-stencil status.
+ *   - Calls on one context must not overlap from several host threads.
+ */
+#ifndef RBFFD_H
+#define RBFFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rbf_status;
+
+/* call return codes */
+#define RBF_OK            0
+#define RBF_EINVAL       -1  /* null pointer or inconsistent argument            */
+#define RBF_ETOOFEW      -2  /* stencil size bound larger than the node count    */
+#define RBF_EDIM         -3  /* dimension not 2 or 3                             */
+#define RBF_EWORKSPACE   -4  /* workspace smaller than the *_workspace size      */
+#define RBF_EHIP         -5  /* HIP runtime error (launch or device)             */
+#define RBF_EUNSUPPORTED -6  /* n_max + m beyond the compiled system sizes       */
+
+/* operator selection (op_mask bits) */
+#define RBF_OP_LAP 1u
+#define RBF_OP_DX  2u
+#define RBF_OP_DY  4u
+#define RBF_OP_DZ  8u
+
+/* per-stencil status values (int8) */
+#define RBF_ST_OK                   0  /* FP64 solve, reproduction check passed      */
+#define RBF_ST_REFINED              1  /* FP32 LU + FP64 refinement accepted         */
+#define RBF_ST_FALLBACK             2  /* refinement rejected, FP64 solve used       */
+#define RBF_ST_SURROGATE            3  /* learned weights accepted after projection  */
+#define RBF_ST_SURROGATE_REJECTED   4  /* learned weights rejected, FP64 solve used  */
+#define RBF_ST_SINGULAR            -1  /* FP64 solve failed its checks: weights NaN  */
+#define RBF_ST_BADSIZE             -2  /* n_i outside [1, n_max]: weights NaN        */
+
+/* precision of the local solves */
+#define RBF_PREC_F64     0  /* LU with partial pivoting in float64                   */
+#define RBF_PREC_F32_IR  1  /* float32 LU + float64-residual iterative refinement   */
+
+typedef struct rbf_ctx rbf_ctx;
+
+typedef struct rbf_options {
+    int    precision;    /* RBF_PREC_F64 or RBF_PREC_F32_IR                           */
+    int    max_refine;   /* refinement corrections for F32_IR (default 10); 0 sends   */
+                         /* every stencil to the FP64 solve                           */
+    int    phs_power;    /* odd exponent k of phi(r) = r^k; 3 (default) or 5          */
+    int    scale_mode;   /* 0: s = max_j |p_j - p*| (default); 1: closest node        */
+    double repro_tol;    /* FP64 reproduction-check tolerance (default 1e-8)          */
+} rbf_options;
+
+/* Default options (precision F64, 10 corrections, r^3, stencil-radius scale). */
+rbf_status rbf_options_default(rbf_options* opt);
+
+/* Human-readable text of a return code (static storage). */
+const char* rbf_status_string(rbf_status s);
+
+/* Context: device ordinal and the HIP stream (hipStream_t, may be NULL for the
+ * default stream) every call is enqueued on.  The context owns no device memory
+ * except the autotuner's plan and the surrogate network parameters. */
+rbf_status rbf_ctx_create(rbf_ctx** ctx, int device, void* hip_stream);
+rbf_status rbf_ctx_set_stream(rbf_ctx* ctx, void* hip_stream);
+rbf_status rbf_ctx_destroy(rbf_ctx* ctx);
+
+/* ------------------------------------------------------------------------ *
+ * Stencil selection (Sec. 2.1, "closest nodes"; FindClosest of Sec. 3.1).
+ *
+ * For node i, idx[offsets[i]] = i and the next n_i - 1 entries are the nodes
+ * j != i with the smallest key ((dx*dx + dy*dy) + dz*dz) in float64 with
+ * dx = x_j - x_i (each operation correctly rounded, no fused multiply-add),
+ * in ascending (key, j) order.  The result is exact (not approximate):
+ * identical to a brute-force search.
+ *
+ * n_max bounds every n_i (1 <= n_max <= min(N, 129)); a node with n_i outside
+ * [1, n_max] gets idx entries -1.  Workspace: rbf_select_stencils_workspace.
+ * ------------------------------------------------------------------------ */
+rbf_status rbf_select_stencils_workspace(int64_t N, int d, int n_max, size_t* bytes);
+rbf_status rbf_select_stencils(rbf_ctx* ctx, const double* X, int64_t N, int d,
+                               const int64_t* offsets, int n_max, int32_t* idx,
+                               void* workspace, size_t ws_bytes);
+
+/* ------------------------------------------------------------------------ *
+ * RBF-FD weights, eq. (rbf-system-aug) of Sec. 2.2.2.
+ *
+ * For each stencil: offsets to the centre p* = X[idx[offsets[i]]], scaled by s
+ * (opt->scale_mode); phi(r) = r^k (opt->phs_power); monomials of total degree
+ * <= degree (m = C(degree + d, d) of them); right-hand sides of the selected
+ * operators at p*; the system is solved (LU with partial pivoting, or FP32 LU
+ * with FP64 refinement and FP64 fallback), the Lagrange multipliers are
+ * discarded and the weights scaled back by s^-2 (LAP) or s^-1 (DX, DY, DZ).
+ * Each stencil's weights pass an FP64 polynomial-reproduction check
+ * (second block row of the system) before they are accepted.
+ *
+ * degree: uniform augmentation degree (0..4).  n_max bounds every n_i; the
+ * system size n_max + m must be <= 128.  status[N] (int8, may be NULL)
+ * receives RBF_ST_*.  w: [popcount(op_mask)][nnz] float64.  DZ requires d = 3.
+ * No workspace is needed.
+ * ------------------------------------------------------------------------ */
+rbf_status rbf_compute_weights(rbf_ctx* ctx, const double* X, int64_t N, int d,
+                               const int64_t* offsets, const int32_t* idx, int64_t nnz,
+                               int n_max, int degree, unsigned op_mask,
+                               const rbf_options* opt, double* w, int8_t* status);
+
+/* ------------------------------------------------------------------------ *
+ * CSR operator (Sec. 2.3.2, internal-node rows of eqs. implicit-start..end).
+ *
+ * row_ptr[N+1] (int64) = offsets; the columns of each row are the stencil
+ * indices in ascending order; vals[r][nnz] holds the weights of operator r
+ * permuted the same way.  n_max bounds every n_i (<= 256).  w and vals may
+ * not alias.  No workspace is needed.
+ * ------------------------------------------------------------------------ */
+rbf_status rbf_assemble_csr(rbf_ctx* ctx, int64_t N, const int64_t* offsets,
+                            const int32_t* idx, const double* w, int n_ops, int64_t nnz,
+                            int n_max, int64_t* row_ptr, int32_t* col, double* vals);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RBFFD_H */

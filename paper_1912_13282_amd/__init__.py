@@ -1,0 +1,14 @@
+"""MI355X-native RBF-FD stencil hot path (Medusa, Slak & Kosec, Sec. 2.1-2.3).
+
+Python face of the HIP library ``librbffd.so`` (C ABI in include/rbffd.h):
+
+    select_stencils  -- exact k-nearest-neighbour stencils, self first
+    compute_weights  -- RBF-FD weights of the augmented PHS + monomial system
+    assemble_csr     -- the sparse operator in CSR form
+
+PyTorch supplies device memory and streams only.
+"""
+from ._binding import (  # noqa: F401
+    OPS, ST_BADSIZE, ST_FALLBACK, ST_OK, ST_REFINED, ST_SINGULAR, ST_SURROGATE, ST_SURROGATE_REJECTED,
+    Context, RbfError, assemble_csr, compute_weights, context, lib, select_stencils,
+)

@@ -1,0 +1,71 @@
+// Host entry point of the RBF-FD weight computation (eq. rbf-system-aug) and the
+// registry of compiled size classes (instantiated in wcls_*.hip).
+#include "weights_kernels.hpp"
+
+#include <math.h>
+
+#include <vector>
+
+namespace rbf {
+
+static std::vector<ClassEntry>& registry() {
+    static std::vector<ClassEntry> r;
+    return r;
+}
+
+void register_class(const ClassEntry& e) { registry().push_back(e); }
+
+const ClassEntry* find_class(int d, int P, int M) {
+    const ClassEntry* best = nullptr;
+    for (const auto& c : registry())
+        if (c.d == d && c.P == P && c.maxm >= M && (!best || c.maxm < best->maxm)) best = &c;
+    return best;
+}
+
+}  // namespace rbf
+
+extern "C" rbf_status rbf_options_default(rbf_options* opt) {
+    if (!opt) return RBF_EINVAL;
+    opt->precision = RBF_PREC_F64;
+    opt->max_refine = 10;
+    opt->phs_power = 3;
+    opt->scale_mode = 0;
+    opt->repro_tol = 1e-8;
+    return RBF_OK;
+}
+
+extern "C" rbf_status rbf_compute_weights(rbf_ctx* ctx, const double* X, int64_t N, int d, const int64_t* offsets,
+                                          const int32_t* idx, int64_t nnz, int n_max, int degree, unsigned op_mask,
+                                          const rbf_options* opt, double* w, int8_t* status) {
+    if (!ctx || !X || !offsets || !idx || !w || N < 1 || nnz < 1) return RBF_EINVAL;
+    if (d != 2 && d != 3) return RBF_EDIM;
+    if (op_mask == 0 || (op_mask & ~0xFu) || (d == 2 && (op_mask & RBF_OP_DZ))) return RBF_EINVAL;
+    if (degree < 0 || degree > 4 || n_max < 1) return RBF_EINVAL;
+    if (n_max > N) return RBF_ETOOFEW;
+    rbf_options o;
+    rbf_options_default(&o);
+    if (opt) o = *opt;
+    if (o.phs_power != 3 && o.phs_power != 5) return RBF_EINVAL;
+    if (o.precision != RBF_PREC_F64 && o.precision != RBF_PREC_F32_IR) return RBF_EINVAL;
+    if (o.precision == RBF_PREC_F32_IR && !status) return RBF_EINVAL;  // the fallback list lives in status
+    if (o.max_refine < 0 || o.scale_mode < 0 || o.scale_mode > 1) return RBF_EINVAL;
+    const int m = n_mono(d, degree);
+    const rbf::ClassEntry* c = rbf::find_class(d, degree, n_max + m);
+    if (!c) return RBF_EUNSUPPORTED;
+    RBF_HIP_CHECK(hipSetDevice(ctx->device));
+    rbf::StencilArgs a;
+    a.X = X;
+    a.N = N;
+    a.offsets = offsets;
+    a.idx = idx;
+    a.nnz = nnz;
+    a.n_max = n_max;
+    a.op_mask = op_mask;
+    a.phs_power = o.phs_power;
+    a.scale_mode = o.scale_mode;
+    a.repro_tol = o.repro_tol;
+    a.w = w;
+    a.status = status;
+    if (c->fn(a, N, o.precision, o.max_refine, ctx->stream) != hipSuccess) return RBF_EHIP;
+    return RBF_OK;
+}

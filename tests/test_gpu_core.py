@@ -1,0 +1,265 @@
+"""GPU parity of the HIP path against the oracle: stencils (bit-exact), FP64 and
+mixed-precision weights (scaled max-norm tolerance), CSR (bit-exact structure).
+
+Tolerance for weights (reading of the stated 1e-10 relative max-norm, scaled by
+h^2 for the Laplacian): E = max_ij h^ord |w_gpu - w_ora| / max(1, max_ij h^ord |w_ora|),
+ord = 2 (Laplacian) or 1 (first derivatives); FP64 path E <= 1e-10, FP32+refine
+E <= 1e-9.
+"""
+import numpy as np
+import pytest
+import torch
+
+import nodesets as ns
+import paper_1912_13282_amd as rb
+from oracle import csr as ocsr
+from oracle import knn as oknn
+from oracle import rbffd as orbf
+
+pytestmark = pytest.mark.gpu
+
+ORD = {"lap": 2, "dx": 1, "dy": 1, "dz": 1}
+
+
+def to_dev(a, dtype, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev, dtype)
+
+
+def scaled_err(wg, wo, ops, off, h):
+    """E of the tolerance definition above."""
+    hn = np.repeat(h, np.diff(off))
+    worst = 0.0
+    for r, op in enumerate(ops):
+        sc = hn ** ORD[op]
+        den = max(1.0, float(np.max(np.abs(wo[r]) * sc)))
+        worst = max(worst, float(np.max(np.abs(wg[r] - wo[r]) * sc)) / den)
+    return worst
+
+
+def run_knn(X, sizes, dev, n_max=None):
+    off = ns.offsets_from_sizes(np.broadcast_to(np.asarray(sizes, np.int64), (X.shape[0],)).copy())
+    n_max = int(np.max(sizes)) if n_max is None else n_max
+    Xd = to_dev(X, torch.float64, dev)
+    od = to_dev(off, torch.int64, dev)
+    idx = rb.select_stencils(Xd, od, n_max)
+    torch.cuda.synchronize()
+    return off, idx.cpu().numpy(), Xd, od, idx
+
+
+# ------------------------------------------------------------------ stencils
+@pytest.mark.parametrize("case", ["disk15", "cube35", "lshape_var", "torus20", "mixed_var129"])
+def test_knn_bit_exact(gpu, case):
+    print(f"[knn] {case}", flush=True)
+    if case == "disk15":
+        X, sizes = ns.disk(0.0404, 1001).X, 15
+    elif case == "cube35":
+        X, sizes = ns.cube_minus_sphere(1.0 / 24, 1002).X, 35
+    elif case == "lshape_var":
+        nd = ns.l_shape(0.02, 5)
+        X, sizes = nd.X, np.random.default_rng(3).integers(1, 71, size=nd.N)
+    elif case == "torus20":
+        X, sizes = ns.torus(0.03, 9).X, 20
+    else:
+        nd = ns.cube_minus_sphere(1.0 / 14, 4)
+        X, sizes = nd.X, np.random.default_rng(8).integers(60, 130, size=nd.N)
+    off, idx, *_ = run_knn(X, sizes, gpu)
+    o2, i2 = oknn.knn_exact(X, sizes)
+    assert np.array_equal(off, o2)
+    assert np.array_equal(idx, i2)
+
+
+def test_knn_lattice_ties(gpu):
+    g = np.array([(i, j) for i in range(5) for j in range(5)], dtype=np.float64) * 2.0 ** -10
+    off, idx, *_ = run_knn(g, 12, gpu)
+    assert idx[off[12]:off[13]].tolist() == [12, 7, 11, 13, 17, 6, 8, 16, 18, 2, 10, 14]
+    o2, i2 = oknn.knn_bruteforce(g, 12)
+    assert np.array_equal(idx, i2)
+
+
+def test_knn_duplicates_and_bad_sizes(gpu):
+    X = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 0.0], [0.0, 2.0], [3.0, 3.0]])
+    sizes = np.array([3, 3, 3, 0, 9])                # 0 and 9 (> n_max) are invalid
+    off = ns.offsets_from_sizes(sizes)
+    idx = rb.select_stencils(to_dev(X, torch.float64, gpu), to_dev(off, torch.int64, gpu), 3).cpu().numpy()
+    assert idx[0:3].tolist() == [0, 2, 1]
+    assert idx[6:9].tolist() == [2, 0, 1]
+    assert np.all(idx[off[4]:off[5]] == -1)
+
+
+def test_knn_full_size_cube_sphere_sampled(gpu):
+    """1.1M-node cube minus sphere, n=35 (the benchmarked workload): sampled nodes vs brute force."""
+    nd = ns.workload("cube_sphere3d")["nodes"][0]
+    off, idx, *_ = run_knn(nd.X, 35, gpu)
+    rng = np.random.default_rng(0)
+    sample = np.concatenate([rng.choice(nd.N, 150, replace=False), np.nonzero(nd.is_boundary)[0][::2000]])
+    allj = np.arange(nd.N)
+    for i in sample:
+        k = oknn.sq_key(nd.X, i, allj)
+        k[i] = np.inf
+        order = np.lexsort((allj, k))[:34]
+        assert idx[off[i]] == i
+        assert np.array_equal(idx[off[i] + 1:off[i + 1]], order), i
+
+
+# ------------------------------------------------------------------ weights
+WEIGHT_CASES = {
+    "disk2d": (lambda: ns.disk(0.0404, 1001), 15, 2, ("lap", "dx", "dy")),
+    "cube3d": (lambda: ns.cube_minus_sphere(1.0 / 20, 1002), 35, 3, ("lap", "dx", "dy", "dz")),
+    "disk2d_n30": (lambda: ns.disk(0.05, 77), 30, 2, ("lap", "dy")),
+}
+
+
+@pytest.mark.parametrize("case", list(WEIGHT_CASES))
+@pytest.mark.parametrize("precision", ["f64", "f32_ir"])
+def test_weights_parity(gpu, case, precision):
+    print(f"[weights] {case} {precision}", flush=True)
+    mk, n, P, ops = WEIGHT_CASES[case]
+    nd = mk()
+    off, idx, Xd, od, idxd = run_knn(nd.X, n, gpu)
+    w, st = rb.compute_weights(Xd, od, idxd, n, P, ops, precision=precision)
+    torch.cuda.synchronize()
+    w, st = w.cpu().numpy(), st.cpu().numpy()
+    wo, sto = orbf.weights(nd.X, off, idx, P, ops)
+    assert sto.min() == 0
+    if precision == "f64":
+        assert np.all(st == rb.ST_OK)
+        tol = 1e-10
+    else:
+        assert np.all((st == rb.ST_REFINED) | (st == rb.ST_FALLBACK))
+        tol = 1e-9
+    E = scaled_err(w, wo, ops, off, nd.h)
+    print(f"  E = {E:.3e}", flush=True)
+    assert E <= tol
+
+
+def test_weights_phs5_and_closest_scale(gpu):
+    nd = ns.unit_square_grid(1 / 24)
+    off, idx, Xd, od, idxd = run_knn(nd.X, 12, gpu)
+    for k, sm in [(5, 0), (3, 1)]:
+        w, st = rb.compute_weights(Xd, od, idxd, 12, 2, ("lap", "dx"), phs_power=k, scale_mode=sm)
+        wo, _ = orbf.weights(nd.X, off, idx, 2, ("lap", "dx"), phs_power=k,
+                             scale="closest" if sm else "max")
+        assert np.all(st.cpu().numpy() == 0)
+        assert scaled_err(w.cpu().numpy(), wo, ("lap", "dx"), off, nd.h) <= 1e-10
+
+
+def test_weights_full_size_cube_sphere_sampled(gpu):
+    """The benchmarked workload at full size (1.1M stencils, n=35, degree 3): every
+    status, and sampled stencils against the oracle, for both precisions."""
+    nd = ns.workload("cube_sphere3d")["nodes"][0]
+    ops = ("lap", "dx", "dy", "dz")
+    off, idx, Xd, od, idxd = run_knn(nd.X, 35, gpu)
+    sample = np.random.default_rng(1).choice(nd.N, 1500, replace=False)
+    ref = orbf.weights_subset(nd.X, off, idx, sample, 3, ops)
+    for precision, tol in [("f64", 1e-10), ("f32_ir", 1e-9)]:
+        w, st = rb.compute_weights(Xd, od, idxd, 35, 3, ops, precision=precision)
+        st = st.cpu().numpy()
+        if precision == "f64":
+            assert np.all(st == 0)
+        else:
+            assert np.all((st == 1) | (st == 2))
+            print(f"  fallback fraction {np.mean(st == 2):.2e}", flush=True)
+        wn = w.cpu().numpy()
+        for i in sample:
+            wg = wn[:, off[i]:off[i + 1]]
+            assert scaled_err(wg, ref[int(i)], ops, np.array([0, 35]), nd.h[i:i + 1]) <= tol
+
+
+def test_ir_forced_fallback_equals_f64(gpu):
+    nd = ns.disk(0.0404, 1001)
+    off, idx, Xd, od, idxd = run_knn(nd.X, 15, gpu)
+    w64, _ = rb.compute_weights(Xd, od, idxd, 15, 2, ("lap", "dx", "dy"))
+    wir, st = rb.compute_weights(Xd, od, idxd, 15, 2, ("lap", "dx", "dy"), precision="f32_ir", max_refine=0)
+    assert torch.all(st == rb.ST_FALLBACK)
+    assert torch.equal(w64, wir)
+
+
+def test_singular_stencil_flagged(gpu):
+    X = np.array([[0.0, 0.0], [0.1, 0.0], [0.0, 0.1], [0.1, 0.1], [0.2, 0.0], [0.0, 0.2], [0.1, 0.0],
+                  [0.3, 0.3]])
+    off = np.array([0, 7, 14], dtype=np.int64)
+    idx = np.array([0, 1, 2, 3, 4, 5, 6, 7, 0, 1, 2, 3, 4, 5], dtype=np.int32)
+    offf = np.zeros(X.shape[0] + 1, dtype=np.int64)
+    offf[1:3] = [7, 14]
+    offf[3:] = 14
+    # nodes 2..7 have empty stencils (status BADSIZE); node 0 is singular (duplicate), node 1 fine
+    Xd, od, idd = to_dev(X, torch.float64, gpu), to_dev(offf, torch.int64, gpu), to_dev(idx, torch.int32, gpu)
+    w, st = rb.compute_weights(Xd, od, idd, 7, 2, ("lap",))
+    st = st.cpu().numpy()
+    w = w.cpu().numpy()
+    assert st[0] == rb.ST_SINGULAR and np.all(np.isnan(w[0, 0:7]))
+    assert st[1] == rb.ST_OK and np.all(np.isfinite(w[0, 7:14]))
+    assert np.all(st[2:] == rb.ST_BADSIZE)
+
+
+# ------------------------------------------------------------------ properties
+def test_gpu_weights_reproduce_polynomials(gpu):
+    nd = ns.cube_minus_sphere(1.0 / 16, 3)
+    off, idx, Xd, od, idxd = run_knn(nd.X, 35, gpu)
+    w, _ = rb.compute_weights(Xd, od, idxd, 35, 3, ("lap", "dx", "dy", "dz"))
+    w = w.cpu().numpy()
+    O = nd.X[idx] - np.repeat(nd.X, 35, axis=0)
+    row = np.repeat(np.arange(nd.N), 35)
+    tests = {"lap": [(np.ones(len(O)), 0.0), (O[:, 0] ** 2, 2.0), (O[:, 0] * O[:, 1], 0.0),
+                     ((O ** 2).sum(1), 6.0), (O[:, 2] ** 3, 0.0)],
+             "dx": [(np.ones(len(O)), 0.0), (O[:, 0], 1.0), (O[:, 1], 0.0), (O[:, 0] ** 2, 0.0)]}
+    for r, op in [(0, "lap"), (1, "dx")]:
+        for vals, ref in tests[op]:
+            s = np.bincount(row, weights=w[r] * vals, minlength=nd.N)
+            a = np.bincount(row, weights=np.abs(w[r] * vals), minlength=nd.N)
+            assert np.all(np.abs(s - ref) <= 1e-9 * (a + abs(ref)))
+
+
+def test_determinism(gpu):
+    nd = ns.cube_minus_sphere(1.0 / 20, 5)
+    runs = []
+    for _ in range(2):
+        off, idx, Xd, od, idxd = run_knn(nd.X, 35, gpu)
+        w, st = rb.compute_weights(Xd, od, idxd, 35, 3, ("lap", "dx"), precision="f32_ir")
+        rp, col, vals = rb.assemble_csr(od, idxd, w, 35)
+        torch.cuda.synchronize()
+        runs.append((idx, w.cpu(), st.cpu(), col.cpu(), vals.cpu()))
+    a, b = runs
+    assert np.array_equal(a[0], b[0])
+    for x, y in zip(a[1:], b[1:]):
+        assert torch.equal(x, y)
+
+
+# ------------------------------------------------------------------ CSR
+@pytest.mark.parametrize("case", ["disk15", "var_sizes", "big_rows"])
+def test_csr_bit_exact(gpu, case):
+    if case == "disk15":
+        X, sizes, P = ns.disk(0.0404, 1001).X, 15, 2
+    elif case == "var_sizes":
+        nd = ns.l_shape(0.03, 2)
+        X, sizes, P = nd.X, np.random.default_rng(4).integers(6, 60, size=nd.N), 2
+    else:
+        nd = ns.cube_minus_sphere(1.0 / 12, 2)
+        X, sizes, P = nd.X, np.random.default_rng(5).integers(60, 200, size=nd.N), 2
+    if np.max(sizes) <= 129:
+        off, idx, Xd, od, idxd = run_knn(X, sizes, gpu)
+    else:
+        # rows beyond the stencil-selection bound: random distinct columns exercise the sort alone
+        rng = np.random.default_rng(6)
+        off = ns.offsets_from_sizes(np.asarray(sizes, np.int64))
+        idx = np.concatenate([rng.choice(X.shape[0], s, replace=False) for s in sizes]).astype(np.int32)
+        od, idxd = to_dev(off, torch.int64, gpu), to_dev(idx, torch.int32, gpu)
+    nnz = int(off[-1])
+    w = torch.randn((2, nnz), dtype=torch.float64, device=gpu)
+    rp, col, vals = rb.assemble_csr(od, idxd, w, int(np.max(sizes)))
+    torch.cuda.synchronize()
+    r2, c2, v2 = ocsr.to_csr(off, idx, w.cpu().numpy())
+    assert np.array_equal(rp.cpu().numpy(), r2)
+    assert np.array_equal(col.cpu().numpy(), c2)
+    assert np.array_equal(vals.cpu().numpy(), v2)
+
+
+def test_csr_of_weights_matches_oracle(gpu):
+    nd = ns.disk(0.0404, 1001)
+    off, idx, Xd, od, idxd = run_knn(nd.X, 15, gpu)
+    w, _ = rb.compute_weights(Xd, od, idxd, 15, 2, ("lap", "dx", "dy"))
+    rp, col, vals = rb.assemble_csr(od, idxd, w, 15)
+    wo, _ = orbf.weights(nd.X, off, idx, 2, ("lap", "dx", "dy"))
+    r2, c2, v2 = ocsr.to_csr(off, idx, wo)
+    assert np.array_equal(col.cpu().numpy(), c2)
+    assert scaled_err(vals.cpu().numpy(), v2, ("lap", "dx", "dy"), off, nd.h) <= 1e-10
