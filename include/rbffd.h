@@ -73,6 +73,9 @@ typedef struct rbf_options {
     int    phs_power;    /* odd exponent k of phi(r) = r^k; 3 (default) or 5          */
     int    scale_mode;   /* 0: s = max_j |p_j - p*| (default); 1: closest node        */
     double repro_tol;    /* FP64 reproduction-check tolerance (default 1e-8)          */
+    double refine_tol;   /* F32_IR acceptance: max|r| <= tol ||K|| max|x| per RHS with */
+                         /* tol = max(sqrt(n+m) 2^-53, refine_tol); 0 (default) is    */
+                         /* LAPACK dsgesv's test                                      */
 } rbf_options;
 
 /* Default options (precision F64, 10 corrections, r^3, stencil-radius scale). */

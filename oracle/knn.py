@@ -41,8 +41,11 @@ def knn_bruteforce(X: np.ndarray, sizes) -> tuple[np.ndarray, np.ndarray]:
     return off, idx
 
 
-def knn_exact(X: np.ndarray, sizes, chunk: int = 65536, extra: int = 8):
+def knn_exact(X: np.ndarray, sizes, chunk: int = 65536, extra: int = 8, nodes=None):
     """Same result as knn_bruteforce for large N.
+
+    With ``nodes`` given, only those nodes' stencils are computed (against all N
+    nodes); offsets and idx then cover the listed nodes in order.
 
     A k-d tree (SciPy) proposes k' candidates per node; the exact FP64 keys of
     the candidates are re-ranked by (key, index).  The selection is exact when
@@ -55,13 +58,16 @@ def knn_exact(X: np.ndarray, sizes, chunk: int = 65536, extra: int = 8):
     X = np.asarray(X, dtype=np.float64)
     N, d = X.shape
     sizes = np.broadcast_to(np.asarray(sizes, dtype=np.int64), (N,))
-    off = np.zeros(N + 1, dtype=np.int64)
-    np.cumsum(sizes, out=off[1:])
+    nodes = np.arange(N) if nodes is None else np.asarray(nodes, dtype=np.int64)
+    slot = np.full(N, -1, dtype=np.int64)          # position of a node in the output
+    slot[nodes] = np.arange(nodes.size)
+    off = np.zeros(nodes.size + 1, dtype=np.int64)
+    np.cumsum(sizes[nodes], out=off[1:])
     idx = np.empty(off[-1], dtype=np.int32)
     tree = cKDTree(X)
-    nmax = int(sizes.max())
+    nmax = int(sizes[nodes].max())
 
-    pending = np.arange(N)
+    pending = nodes.copy()
     kq = nmax + extra
     while pending.size:
         kq_eff = min(kq, N)
@@ -86,7 +92,7 @@ def knn_exact(X: np.ndarray, sizes, chunk: int = 65536, extra: int = 8):
             redo.append(Q[~ok])
             for nv in np.unique(ni[ok]):
                 rows = np.nonzero(ok & (ni == nv))[0]
-                base = off[Q[rows]]
+                base = off[slot[Q[rows]]]
                 idx[base] = Q[rows]
                 if nv > 1:
                     pos = base[:, None] + np.arange(1, nv)[None, :]

@@ -33,7 +33,7 @@ class RbfError(RuntimeError):
 
 class rbf_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("max_refine", ctypes.c_int), ("phs_power", ctypes.c_int),
-                ("scale_mode", ctypes.c_int), ("repro_tol", ctypes.c_double)]
+                ("scale_mode", ctypes.c_int), ("repro_tol", ctypes.c_double), ("refine_tol", ctypes.c_double)]
 
 
 _P = ctypes.c_void_p
@@ -121,7 +121,8 @@ def context(device=None) -> Context:
     return _ctx_cache[key]
 
 
-def options(precision="f64", max_refine=10, phs_power=3, scale_mode=0, repro_tol=1e-8) -> rbf_options:
+def options(precision="f64", max_refine=10, phs_power=3, scale_mode=0, repro_tol=1e-8,
+            refine_tol=0.0) -> rbf_options:
     o = rbf_options()
     _check(lib().rbf_options_default(ctypes.byref(o)), "rbf_options_default")
     o.precision = PREC[precision]
@@ -129,6 +130,7 @@ def options(precision="f64", max_refine=10, phs_power=3, scale_mode=0, repro_tol
     o.phs_power = int(phs_power)
     o.scale_mode = int(scale_mode)
     o.repro_tol = float(repro_tol)
+    o.refine_tol = float(refine_tol)
     return o
 
 

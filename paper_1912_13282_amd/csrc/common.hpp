@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "../../include/rbffd.h"
 
 struct rbf_ctx {
@@ -82,6 +84,59 @@ __device__ __forceinline__ float wave_max_f(float v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
     return v;
+}
+
+// DPP move of a double (each 32-bit half with the same control); rows outside
+// row_mask keep their own value.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_d(double v) {
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    lo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xF, false);
+    hi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(v), __float_as_int(v), CTRL, ROW_MASK, 0xF, false));
+}
+
+// Wave-wide maximum through DPP (quad xor 1, xor 2, half-row mirror, row mirror,
+// row broadcast 15 / 31); the total ends in lane 63 and is returned uniformly.
+__device__ __forceinline__ double wave_max_dpp_d(double v) {
+    v = fmax(v, dpp_d<0xB1, 0xF>(v));
+    v = fmax(v, dpp_d<0x4E, 0xF>(v));
+    v = fmax(v, dpp_d<0x141, 0xF>(v));
+    v = fmax(v, dpp_d<0x140, 0xF>(v));
+    v = fmax(v, dpp_d<0x142, 0xA>(v));
+    v = fmax(v, dpp_d<0x143, 0xC>(v));
+    return readlane_d(v, 63);
+}
+__device__ __forceinline__ float wave_max_dpp_f(float v) {
+    v = fmaxf(v, dpp_f<0xB1, 0xF>(v));
+    v = fmaxf(v, dpp_f<0x4E, 0xF>(v));
+    v = fmaxf(v, dpp_f<0x141, 0xF>(v));
+    v = fmaxf(v, dpp_f<0x140, 0xF>(v));
+    v = fmaxf(v, dpp_f<0x142, 0xA>(v));
+    v = fmaxf(v, dpp_f<0x143, 0xC>(v));
+    return readlane_f(v, 63);
+}
+// Wave-wide sum through DPP in a fixed order (deterministic); uniform result.
+__device__ __forceinline__ double wave_sum_dpp_d(double v) {
+    v += dpp_d<0xB1, 0xF>(v);
+    v += dpp_d<0x4E, 0xF>(v);
+    v += dpp_d<0x141, 0xF>(v);
+    v += dpp_d<0x140, 0xF>(v);
+    // rows now hold their row sums; combine the four rows in a fixed order
+    double r0 = readlane_d(v, 0), r1 = readlane_d(v, 16), r2 = readlane_d(v, 32), r3 = readlane_d(v, 48);
+    return (r0 + r1) + (r2 + r3);
+}
+
+// LDS visibility of this wave's own stores to its other lanes (LDS operations of
+// one wavefront execute in order; the fences stop the compiler from moving them).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // first set lane of a wave-uniform 64-bit mask (mask != 0)

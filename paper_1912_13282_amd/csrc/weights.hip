@@ -31,6 +31,7 @@ extern "C" rbf_status rbf_options_default(rbf_options* opt) {
     opt->phs_power = 3;
     opt->scale_mode = 0;
     opt->repro_tol = 1e-8;
+    opt->refine_tol = 0.0;
     return RBF_OK;
 }
 
@@ -48,7 +49,7 @@ extern "C" rbf_status rbf_compute_weights(rbf_ctx* ctx, const double* X, int64_t
     if (o.phs_power != 3 && o.phs_power != 5) return RBF_EINVAL;
     if (o.precision != RBF_PREC_F64 && o.precision != RBF_PREC_F32_IR) return RBF_EINVAL;
     if (o.precision == RBF_PREC_F32_IR && !status) return RBF_EINVAL;  // the fallback list lives in status
-    if (o.max_refine < 0 || o.scale_mode < 0 || o.scale_mode > 1) return RBF_EINVAL;
+    if (o.max_refine < 0 || o.scale_mode < 0 || o.scale_mode > 1 || !(o.refine_tol >= 0.0)) return RBF_EINVAL;
     const int m = n_mono(d, degree);
     const rbf::ClassEntry* c = rbf::find_class(d, degree, n_max + m);
     if (!c) return RBF_EUNSUPPORTED;
@@ -66,6 +67,6 @@ extern "C" rbf_status rbf_compute_weights(rbf_ctx* ctx, const double* X, int64_t
     a.repro_tol = o.repro_tol;
     a.w = w;
     a.status = status;
-    if (c->fn(a, N, o.precision, o.max_refine, ctx->stream) != hipSuccess) return RBF_EHIP;
+    if (c->fn(a, N, o.precision, o.max_refine, o.refine_tol, ctx->stream) != hipSuccess) return RBF_EHIP;
     return RBF_OK;
 }

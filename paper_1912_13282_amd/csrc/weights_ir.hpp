@@ -42,8 +42,8 @@ __device__ __forceinline__ bool repro_ok(const StencilArgs& a, int n, const Fram
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
         if (!(a.op_mask & (1u << q))) continue;
-        double s = wave_sum_d(S[q]);
-        double ab = wave_sum_d(A[q]);
+        double s = wave_sum_dpp_d(S[q]);
+        double ab = wave_sum_dpp_d(A[q]);
         double lp = 0.0;
 #pragma unroll
         for (int l = 0; l < m; ++l) lp += check_coef(l) * MO.lq(l, q);
