@@ -121,8 +121,10 @@ rbf_status rbf_select_stencils(rbf_ctx* ctx, const double* X, int64_t N, int d,
  * (second block row of the system) before they are accepted.
  *
  * degree: uniform augmentation degree (0..4).  n_max bounds every n_i; the
- * system size n_max + m must be <= 128.  status[N] (int8, may be NULL)
- * receives RBF_ST_*.  w: [popcount(op_mask)][nnz] float64.  DZ requires d = 3.
+ * system size n_max + m must be <= 128.  Systems above 64 unknowns are solved
+ * in float64 (LU, two rows per lane) also when F32_IR is asked for, and then
+ * report RBF_ST_FALLBACK.  status[N] (int8, may be NULL for F64) receives
+ * RBF_ST_*.  w: [popcount(op_mask)][nnz] float64.  DZ requires d = 3.
  * No workspace is needed.
  * ------------------------------------------------------------------------ */
 rbf_status rbf_compute_weights(rbf_ctx* ctx, const double* X, int64_t N, int d,
@@ -141,6 +143,53 @@ rbf_status rbf_compute_weights(rbf_ctx* ctx, const double* X, int64_t N, int d,
 rbf_status rbf_assemble_csr(rbf_ctx* ctx, int64_t N, const int64_t* offsets,
                             const int32_t* idx, const double* w, int n_ops, int64_t nnz,
                             int n_max, int64_t* row_ptr, int32_t* col, double* vals);
+
+/* ------------------------------------------------------------------------ *
+ * Batched persistent form: the weights of several node sets at once, mixing
+ * dimension (2D/3D), augmentation degree (2..4, per node) and stencil size,
+ * in one persistent launch per precision (the FP32+refine form adds a second
+ * launch for its FP64 fallbacks).  Each domain is described as for
+ * rbf_compute_weights; every stencil's system size n_i + m must be <= 128.
+ * Results, status codes and layouts are those of rbf_compute_weights.
+ * Workspace: rbf_batched_workspace.  The plan (chunk of stencils per grab,
+ * waves per compute unit) is the context's, set by rbf_autotune_batched or
+ * rbf_set_plan (default chunk 4, 8 waves per CU).  At most 16 domains.
+ * ------------------------------------------------------------------------ */
+typedef struct rbf_domain_desc {
+    const double*  X;              /* [N][d] node coordinates                        */
+    int64_t        N;
+    int            d;              /* 2 or 3                                         */
+    const int64_t* offsets;        /* [N+1]                                          */
+    const int32_t* idx;            /* [nnz] stencils, centre first                   */
+    int64_t        nnz;
+    const int8_t*  degree;         /* [N] per-node augmentation degree, or NULL      */
+    int            degree_uniform; /* degree of every node when degree == NULL       */
+    int            n_max;          /* bound on every n_i                             */
+    unsigned       op_mask;        /* RBF_OP_* of this domain                        */
+    double*        w;              /* [popcount(op_mask)][nnz] output                */
+    int8_t*        status;         /* [N] output (required)                          */
+} rbf_domain_desc;
+
+typedef struct rbf_plan {
+    int   chunk;         /* stencils taken per atomic grab of the work list   */
+    int   waves_per_cu;  /* persistent grid size = compute units x this       */
+    float ms;            /* time of the plan when it was tuned (0 if set)     */
+} rbf_plan;
+
+rbf_status rbf_batched_workspace(const rbf_domain_desc* doms, int n_doms, size_t* bytes);
+rbf_status rbf_compute_weights_batched(rbf_ctx* ctx, const rbf_domain_desc* doms, int n_doms,
+                                       const rbf_options* opt, void* workspace, size_t ws_bytes);
+
+/* Autotuner of the batched form: times every candidate plan (chunk in
+ * {1,2,4,8,16} x waves per CU in {4,8,12,16}) on this batch, stores the fastest
+ * in the context and returns it.  Synchronous.  cache_path (host string, may be
+ * NULL): a text file of "signature chunk waves ms" lines; a stored plan for the
+ * same device and batch signature is reused without timing, a tuned one appended. */
+rbf_status rbf_autotune_batched(rbf_ctx* ctx, const rbf_domain_desc* doms, int n_doms,
+                                const rbf_options* opt, void* workspace, size_t ws_bytes,
+                                const char* cache_path, rbf_plan* best);
+rbf_status rbf_set_plan(rbf_ctx* ctx, const rbf_plan* plan);   /* NULL: back to the default */
+rbf_status rbf_get_plan(const rbf_ctx* ctx, rbf_plan* plan);
 
 #ifdef __cplusplus
 }

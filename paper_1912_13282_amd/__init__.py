@@ -5,10 +5,13 @@ Python face of the HIP library ``librbffd.so`` (C ABI in include/rbffd.h):
     select_stencils  -- exact k-nearest-neighbour stencils, self first
     compute_weights  -- RBF-FD weights of the augmented PHS + monomial system
     assemble_csr     -- the sparse operator in CSR form
+    compute_weights_batched / autotune_batched
+                     -- mixed 2D/3D, per-node degree and size in one persistent launch
 
 PyTorch supplies device memory and streams only.
 """
 from ._binding import (  # noqa: F401
     OPS, ST_BADSIZE, ST_FALLBACK, ST_OK, ST_REFINED, ST_SINGULAR, ST_SURROGATE, ST_SURROGATE_REJECTED,
-    Context, RbfError, assemble_csr, compute_weights, context, lib, select_stencils,
+    Context, Domain, RbfError, assemble_csr, autotune_batched, compute_weights, compute_weights_batched, context,
+    get_plan, lib, select_stencils, set_plan,
 )

@@ -36,6 +36,17 @@ class rbf_options(ctypes.Structure):
                 ("scale_mode", ctypes.c_int), ("repro_tol", ctypes.c_double), ("refine_tol", ctypes.c_double)]
 
 
+class rbf_domain_desc(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("N", ctypes.c_int64), ("d", ctypes.c_int), ("offsets", ctypes.c_void_p),
+                ("idx", ctypes.c_void_p), ("nnz", ctypes.c_int64), ("degree", ctypes.c_void_p),
+                ("degree_uniform", ctypes.c_int), ("n_max", ctypes.c_int), ("op_mask", ctypes.c_uint),
+                ("w", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+
+class rbf_plan(ctypes.Structure):
+    _fields_ = [("chunk", ctypes.c_int), ("waves_per_cu", ctypes.c_int), ("ms", ctypes.c_float)]
+
+
 _P = ctypes.c_void_p
 _I64 = ctypes.c_int64
 _I = ctypes.c_int
@@ -52,6 +63,12 @@ _SIGS = {
     "rbf_select_stencils": [_P, _P, _I64, _I, _P, _I, _P, _P, _SZ],
     "rbf_compute_weights": [_P, _P, _I64, _I, _P, _P, _I64, _I, _I, _U, ctypes.POINTER(rbf_options), _P, _P],
     "rbf_assemble_csr": [_P, _I64, _P, _P, _P, _I, _I64, _I, _P, _P, _P],
+    "rbf_batched_workspace": [ctypes.POINTER(rbf_domain_desc), _I, ctypes.POINTER(_SZ)],
+    "rbf_compute_weights_batched": [_P, ctypes.POINTER(rbf_domain_desc), _I, ctypes.POINTER(rbf_options), _P, _SZ],
+    "rbf_autotune_batched": [_P, ctypes.POINTER(rbf_domain_desc), _I, ctypes.POINTER(rbf_options), _P, _SZ,
+                             ctypes.c_char_p, ctypes.POINTER(rbf_plan)],
+    "rbf_set_plan": [_P, ctypes.POINTER(rbf_plan)],
+    "rbf_get_plan": [_P, ctypes.POINTER(rbf_plan)],
 }
 
 
@@ -210,3 +227,100 @@ def assemble_csr(offsets: torch.Tensor, idx: torch.Tensor, w: torch.Tensor | Non
                                   _dev(row_ptr, torch.int64, "row_ptr"), _dev(col, torch.int32, "col"), pv),
            "rbf_assemble_csr")
     return row_ptr, col, vals
+
+
+# ------------------------------------------------------------------ batched form
+class Domain:
+    """One node set of a batched call: device tensors and stencil parameters.
+
+    X [N, d] float64, offsets [N+1] int64, idx [nnz] int32, degree [N] int8 (or
+    an int for a uniform degree), ops: tuple of operator names.  Outputs w and
+    status are allocated on first use.
+    """
+
+    def __init__(self, X, offsets, idx, n_max, degree, ops):
+        self.X, self.offsets, self.idx, self.n_max = X, offsets, idx, int(n_max)
+        self.degree = degree
+        self.ops = tuple(o for o in OPS if o in ops)
+        self.w = torch.empty((len(self.ops), idx.numel()), dtype=torch.float64, device=X.device)
+        self.status = torch.empty(X.shape[0], dtype=torch.int8, device=X.device)
+
+    def desc(self) -> rbf_domain_desc:
+        D = rbf_domain_desc()
+        D.X = _dev(self.X, torch.float64, "X")
+        D.N = self.X.shape[0]
+        D.d = self.X.shape[1]
+        D.offsets = _dev(self.offsets, torch.int64, "offsets")
+        D.idx = _dev(self.idx, torch.int32, "idx")
+        D.nnz = self.idx.numel()
+        if isinstance(self.degree, torch.Tensor):
+            D.degree = _dev(self.degree, torch.int8, "degree")
+            D.degree_uniform = 0
+        else:
+            D.degree = None
+            D.degree_uniform = int(self.degree)
+        D.n_max = self.n_max
+        D.op_mask = op_mask(self.ops)
+        D.w = _dev(self.w, torch.float64, "w")
+        D.status = _dev(self.status, torch.int8, "status")
+        return D
+
+
+def _descs(domains):
+    arr = (rbf_domain_desc * len(domains))()
+    for k, d in enumerate(domains):
+        arr[k] = d.desc()
+    return arr
+
+
+def batched_workspace(domains) -> int:
+    b = _SZ()
+    arr = _descs(domains)
+    _check(lib().rbf_batched_workspace(arr, len(domains), ctypes.byref(b)), "rbf_batched_workspace")
+    return b.value
+
+
+def compute_weights_batched(domains, precision="f64", workspace=None, ctx: Context | None = None, **opt):
+    """Weights of every domain in one persistent launch (per precision); results in domain.w/.status."""
+    ctx = ctx or context(domains[0].X.device)
+    arr = _descs(domains)
+    nb = batched_workspace(domains)
+    if workspace is None or workspace.numel() < nb:
+        workspace = torch.empty(nb, dtype=torch.uint8, device=domains[0].X.device)
+    o = options(precision=precision, **opt)
+    _check(lib().rbf_compute_weights_batched(ctx._sync_stream(), arr, len(domains), ctypes.byref(o),
+                                             _dev(workspace, torch.uint8, "workspace"), workspace.numel()),
+           "rbf_compute_weights_batched")
+    return domains
+
+
+def autotune_batched(domains, precision="f64", cache_path=None, workspace=None, ctx: Context | None = None, **opt):
+    """Time the candidate plans on this batch; the fastest becomes the context's plan."""
+    ctx = ctx or context(domains[0].X.device)
+    arr = _descs(domains)
+    nb = batched_workspace(domains)
+    if workspace is None or workspace.numel() < nb:
+        workspace = torch.empty(nb, dtype=torch.uint8, device=domains[0].X.device)
+    o = options(precision=precision, **opt)
+    plan = rbf_plan()
+    cp = cache_path.encode() if cache_path else None
+    _check(lib().rbf_autotune_batched(ctx._sync_stream(), arr, len(domains), ctypes.byref(o),
+                                      _dev(workspace, torch.uint8, "workspace"), workspace.numel(), cp,
+                                      ctypes.byref(plan)), "rbf_autotune_batched")
+    return {"chunk": plan.chunk, "waves_per_cu": plan.waves_per_cu, "ms": plan.ms}
+
+
+def set_plan(chunk=None, waves_per_cu=None, ctx: Context | None = None, device=None):
+    ctx = ctx or context(device)
+    if chunk is None:
+        _check(lib().rbf_set_plan(ctx._h, None), "rbf_set_plan")
+        return
+    p = rbf_plan(int(chunk), int(waves_per_cu), 0.0)
+    _check(lib().rbf_set_plan(ctx._h, ctypes.byref(p)), "rbf_set_plan")
+
+
+def get_plan(ctx: Context | None = None, device=None):
+    ctx = ctx or context(device)
+    p = rbf_plan()
+    _check(lib().rbf_get_plan(ctx._h, ctypes.byref(p)), "rbf_get_plan")
+    return {"chunk": p.chunk, "waves_per_cu": p.waves_per_cu}

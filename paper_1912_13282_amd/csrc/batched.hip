@@ -1,0 +1,387 @@
+// Batched persistent RBF-FD weights: stencils of several node sets, mixed
+// dimension (2D/3D), augmentation degree (2..4) and size, in ONE persistent
+// launch per precision.
+//
+//   k_bclassify : class of every stencil = (d, degree, size bucket); counts
+//   k_bscan     : class offsets (one block)
+//   k_bscatter  : class-sorted work list of (domain, node) items
+//   k_bpersist  : a fixed grid of single-wave workgroups; each wave grabs
+//                 `chunk` items at a time from an atomic counter (so uneven
+//                 stencils balance dynamically) and runs the class's solver:
+//                 size bucket <= 64 -> one row per lane Gauss-Jordan with the
+//                 runtime system size guarded; <= 128 -> two rows per lane LU.
+// The work list is sorted by class, so waves running at the same time mostly
+// execute the same code.  The plan (chunk, waves per CU) comes from
+// rbf_autotune_batched, which times candidate plans on the caller's batch.
+#include "weights_kernels.hpp"
+
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <chrono>
+#include <string>
+#include <vector>
+
+namespace rbf {
+
+constexpr int BMAX_DOMS = 16;
+constexpr int SMALL = 64;
+constexpr int BIG = 128;
+constexpr int NCLS = 2 * 3 * 2;  // d in {2,3} x degree in {2,3,4} x bucket in {<=64, <=112}
+constexpr int REJECT = NCLS;     // invalid stencils (bad size / degree / index)
+
+__host__ __device__ constexpr int cls_id(int d, int P, int big) { return ((d - 2) * 3 + (P - 2)) * 2 + big; }
+
+struct BDom {
+    StencilArgs a;         // a.d is the domain's dimension, a.P its uniform degree
+    const int8_t* degree;  // per-node degree, or NULL
+    int64_t first;         // first global item of this domain
+};
+
+struct BParams {
+    int n_doms;
+    int64_t total;
+    BDom dom[BMAX_DOMS];
+};
+
+__device__ __forceinline__ int find_dom(const BParams& bp, int64_t g) {
+    int d = 0;
+    for (int k = 1; k < bp.n_doms; ++k)
+        if (g >= bp.dom[k].first) d = k;
+    return d;
+}
+
+__global__ __launch_bounds__(256) void k_bclassify(const BParams* __restrict__ bpp, int* __restrict__ counts,
+                                                   uint32_t* __restrict__ cls_rank) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const BParams& bp = *bpp;
+    if (g >= bp.total) return;
+    const int di = find_dom(bp, g);
+    const BDom& D = bp.dom[di];
+    const int64_t i = g - D.first;
+    const int P = D.degree ? (int)D.degree[i] : D.a.P;
+    const int64_t n = D.a.offsets[i + 1] - D.a.offsets[i];
+    int c = REJECT;
+    if (P >= 2 && P <= 4 && n >= 1 && n <= D.a.n_max) {
+        const int M = (int)n + binom(P + D.a.d, D.a.d);
+        if (M <= BIG) c = cls_id(D.a.d, P, M > SMALL ? 1 : 0);
+    }
+    const int r = atomicAdd(&counts[c], 1);
+    cls_rank[2 * g] = (uint32_t)c;
+    cls_rank[2 * g + 1] = (uint32_t)r;
+}
+
+__global__ __launch_bounds__(64) void k_bscan(const int* __restrict__ counts, int64_t* __restrict__ starts,
+                                              unsigned long long* __restrict__ counter) {
+    if (threadIdx.x == 0) {
+        int64_t s = 0;
+        for (int c = 0; c <= NCLS; ++c) {
+            starts[c] = s;
+            s += counts[c];
+        }
+        starts[NCLS + 1] = s;
+        counter[0] = 0;
+        counter[1] = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bscatter(const BParams* __restrict__ bpp, const uint32_t* __restrict__ cls_rank,
+                                                  const int64_t* __restrict__ starts, uint64_t* __restrict__ items) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= bpp->total) return;
+    const uint32_t c = cls_rank[2 * g], r = cls_rank[2 * g + 1];
+    items[starts[c] + r] = (uint64_t)g;
+}
+
+// LDS (in doubles) of the largest solver in the batch
+constexpr int BLDS = RowLds<SMALL>::TOTAL > big_lds_doubles<BIG>() ? RowLds<SMALL>::TOTAL : big_lds_doubles<BIG>();
+
+// class c -> solver: one row per lane (guarded Gauss-Jordan) for the <= 64
+// bucket, two rows per lane float64 LU for the <= 128 bucket
+template <int PREC>
+__device__ __forceinline__ void run_class(int c, const StencilArgs& a, int64_t node, int P, double* lds,
+                                          int max_refine, double refine_tol) {
+    if (c >= NCLS) {
+        const int64_t off = a.offsets[node];
+        const int64_t n = a.offsets[node + 1] - off;
+        reject_stencil(a, node, off, (n < 0 || off < 0 || off + n > a.nnz) ? 0 : n, RBF_ST_BADSIZE);
+    } else if (c & 1) {
+        stencil_f64_big<BIG>(a, node, P, lds);
+    } else if constexpr (PREC == RBF_PREC_F64) {
+        stencil_f64_rows<SMALL, true>(a, node, P, lds);
+    } else {
+        stencil_ir_rows<SMALL, true>(a, node, P, lds, max_refine, refine_tol);
+    }
+}
+
+// fallback_pass: solve (float64) only the items whose status is FALLBACK
+template <int PREC>
+__global__ __launch_bounds__(64) void k_bpersist(const BParams* __restrict__ bpp, const uint64_t* __restrict__ items,
+                                                 const int64_t* __restrict__ starts,
+                                                 unsigned long long* __restrict__ counter, int chunk, int max_refine,
+                                                 double refine_tol, int fallback_pass) {
+    __shared__ __attribute__((aligned(16))) double lds[BLDS];
+    const BParams& bp = *bpp;
+    const int64_t total = starts[NCLS + 1];
+    int64_t cst[NCLS + 2];
+    for (int c = 0; c <= NCLS + 1; ++c) cst[c] = starts[c];
+    for (;;) {
+        unsigned long long base = 0;
+        if (lane_id() == 0) base = atomicAdd(counter, (unsigned long long)chunk);
+        base = __builtin_amdgcn_readfirstlane((int)(base & 0xFFFFFFFFull)) |
+               ((unsigned long long)__builtin_amdgcn_readfirstlane((int)(base >> 32)) << 32);
+        if ((int64_t)base >= total) break;  // every wave leaves once the list is drained
+        const int64_t end = ((int64_t)base + chunk < total) ? (int64_t)base + chunk : total;
+        for (int64_t t = (int64_t)base; t < end; ++t) {
+            const uint64_t g = items[t];
+            int c = 0;
+            for (int k = 1; k <= NCLS; ++k)
+                if ((int64_t)t >= cst[k]) c = k;
+            const int di = find_dom(bp, (int64_t)g);
+            const BDom& D = bp.dom[di];
+            const int64_t node = (int64_t)g - D.first;
+            const int P = D.degree ? (int)D.degree[node] : D.a.P;
+            if (fallback_pass) {
+                if (D.a.status[node] != RBF_ST_FALLBACK) continue;
+                run_class<RBF_PREC_F64>(c, D.a, node, P, lds, 0, 0.0);
+                if (lane_id() == 0 && D.a.status[node] == RBF_ST_OK) D.a.status[node] = RBF_ST_FALLBACK;
+            } else if (PREC == RBF_PREC_F32_IR && c < NCLS && (c & 1)) {
+                // the <= 128 bucket has no float32 solver: the fallback pass
+                // solves it in float64
+                if (lane_id() == 0) D.a.status[node] = RBF_ST_FALLBACK;
+            } else {
+                run_class<PREC>(c, D.a, node, P, lds, max_refine, refine_tol);
+            }
+        }
+    }
+}
+
+struct BLayout {
+    size_t params, counts, starts, counter, cls_rank, items, total;
+};
+
+BLayout blayout(int64_t total) {
+    BLayout L;
+    size_t o = 0;
+    L.params = o;
+    o += rbf_align(sizeof(BParams));
+    L.counts = o;
+    o += rbf_align(sizeof(int) * (NCLS + 2));
+    L.starts = o;
+    o += rbf_align(sizeof(int64_t) * (NCLS + 2));
+    L.counter = o;
+    o += rbf_align(sizeof(unsigned long long) * 2);
+    L.cls_rank = o;
+    o += rbf_align(sizeof(uint32_t) * 2 * total);
+    L.items = o;
+    o += rbf_align(sizeof(uint64_t) * total);
+    L.total = o;
+    return L;
+}
+
+rbf_status check_doms(const rbf_domain_desc* doms, int n_doms, int64_t* total) {
+    if (!doms || n_doms < 1 || n_doms > BMAX_DOMS) return RBF_EINVAL;
+    int64_t t = 0;
+    for (int k = 0; k < n_doms; ++k) {
+        const rbf_domain_desc& D = doms[k];
+        if (!D.X || !D.offsets || !D.idx || !D.w || !D.status || D.N < 1 || D.nnz < 1 || D.n_max < 1) return RBF_EINVAL;
+        if (D.d != 2 && D.d != 3) return RBF_EDIM;
+        if (D.op_mask == 0 || (D.op_mask & ~0xFu) || (D.d == 2 && (D.op_mask & RBF_OP_DZ))) return RBF_EINVAL;
+        if (!D.degree && (D.degree_uniform < 2 || D.degree_uniform > 4)) return RBF_EUNSUPPORTED;
+        if (D.n_max > D.N) return RBF_ETOOFEW;
+        t += D.N;
+    }
+    *total = t;
+    return RBF_OK;
+}
+
+// Enqueue the batched computation with a given plan.
+rbf_status run_batched(rbf_ctx* ctx, const rbf_domain_desc* doms, int n_doms, const rbf_options& o, void* ws,
+                       size_t ws_bytes, int chunk, int waves_per_cu) {
+    int64_t total = 0;
+    rbf_status st = check_doms(doms, n_doms, &total);
+    if (st != RBF_OK) return st;
+    BLayout L = blayout(total);
+    if (!ws || ws_bytes < L.total) return RBF_EWORKSPACE;
+    char* w = (char*)ws;
+    BParams bp;
+    memset(&bp, 0, sizeof(bp));
+    bp.n_doms = n_doms;
+    bp.total = total;
+    int64_t first = 0;
+    for (int k = 0; k < n_doms; ++k) {
+        const rbf_domain_desc& D = doms[k];
+        BDom& B = bp.dom[k];
+        B.a.X = D.X;
+        B.a.N = D.N;
+        B.a.offsets = D.offsets;
+        B.a.idx = D.idx;
+        B.a.nnz = D.nnz;
+        B.a.n_max = D.n_max;
+        B.a.op_mask = D.op_mask;
+        B.a.phs_power = o.phs_power;
+        B.a.scale_mode = o.scale_mode;
+        B.a.repro_tol = o.repro_tol;
+        B.a.w = D.w;
+        B.a.status = D.status;
+        B.a.d = D.d;
+        B.a.P = D.degree_uniform;
+        B.degree = D.degree;
+        B.first = first;
+        first += D.N;
+    }
+    hipStream_t s = ctx->stream;
+    BParams* dbp = (BParams*)(w + L.params);
+    int* counts = (int*)(w + L.counts);
+    int64_t* starts = (int64_t*)(w + L.starts);
+    unsigned long long* counter = (unsigned long long*)(w + L.counter);
+    uint32_t* cls_rank = (uint32_t*)(w + L.cls_rank);
+    uint64_t* items = (uint64_t*)(w + L.items);
+    RBF_HIP_CHECK(hipMemcpyAsync(dbp, &bp, sizeof(bp), hipMemcpyHostToDevice, s));
+    RBF_HIP_CHECK(hipMemsetAsync(counts, 0, sizeof(int) * (NCLS + 2), s));
+    const unsigned nb = (unsigned)((total + 255) / 256);
+    hipLaunchKernelGGL(k_bclassify, dim3(nb), dim3(256), 0, s, dbp, counts, cls_rank);
+    hipLaunchKernelGGL(k_bscan, dim3(1), dim3(64), 0, s, counts, starts, counter);
+    hipLaunchKernelGGL(k_bscatter, dim3(nb), dim3(256), 0, s, dbp, cls_rank, starts, items);
+    int cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) cus = prop.multiProcessorCount;
+    const unsigned grid = (unsigned)(cus * waves_per_cu);
+    if (o.precision == RBF_PREC_F64) {
+        hipLaunchKernelGGL((k_bpersist<RBF_PREC_F64>), dim3(grid), dim3(64), 0, s, dbp, items, starts, counter, chunk,
+                           o.max_refine, o.refine_tol, 0);
+    } else {
+        hipLaunchKernelGGL((k_bpersist<RBF_PREC_F32_IR>), dim3(grid), dim3(64), 0, s, dbp, items, starts, counter,
+                           chunk, o.max_refine, o.refine_tol, 0);
+        hipLaunchKernelGGL((k_bpersist<RBF_PREC_F64>), dim3(grid), dim3(64), 0, s, dbp, items, starts, counter + 1,
+                           chunk, o.max_refine, o.refine_tol, 1);
+    }
+    RBF_LAUNCH_CHECK();
+    return RBF_OK;
+}
+
+}  // namespace rbf
+
+extern "C" rbf_status rbf_batched_workspace(const rbf_domain_desc* doms, int n_doms, size_t* bytes) {
+    if (!bytes) return RBF_EINVAL;
+    int64_t total = 0;
+    rbf_status st = rbf::check_doms(doms, n_doms, &total);
+    if (st != RBF_OK) return st;
+    *bytes = rbf::blayout(total).total;
+    return RBF_OK;
+}
+
+extern "C" rbf_status rbf_compute_weights_batched(rbf_ctx* ctx, const rbf_domain_desc* doms, int n_doms,
+                                                  const rbf_options* opt, void* workspace, size_t ws_bytes) {
+    if (!ctx) return RBF_EINVAL;
+    rbf_options o;
+    rbf_options_default(&o);
+    if (opt) o = *opt;
+    if (o.precision != RBF_PREC_F64 && o.precision != RBF_PREC_F32_IR) return RBF_EINVAL;
+    if ((o.phs_power != 3 && o.phs_power != 5) || o.max_refine < 0 || !(o.refine_tol >= 0.0)) return RBF_EINVAL;
+    RBF_HIP_CHECK(hipSetDevice(ctx->device));
+    const int chunk = ctx->plan_valid ? ctx->plan_chunk : 4;
+    const int wpc = ctx->plan_valid ? ctx->plan_waves_per_cu : 8;
+    return rbf::run_batched(ctx, doms, n_doms, o, workspace, ws_bytes, chunk, wpc);
+}
+
+extern "C" rbf_status rbf_set_plan(rbf_ctx* ctx, const rbf_plan* plan) {
+    if (!ctx) return RBF_EINVAL;
+    if (!plan) {
+        ctx->plan_valid = 0;
+        return RBF_OK;
+    }
+    if (plan->chunk < 1 || plan->chunk > 4096 || plan->waves_per_cu < 1 || plan->waves_per_cu > 64) return RBF_EINVAL;
+    ctx->plan_valid = 1;
+    ctx->plan_chunk = plan->chunk;
+    ctx->plan_waves_per_cu = plan->waves_per_cu;
+    return RBF_OK;
+}
+
+extern "C" rbf_status rbf_get_plan(const rbf_ctx* ctx, rbf_plan* plan) {
+    if (!ctx || !plan) return RBF_EINVAL;
+    plan->chunk = ctx->plan_valid ? ctx->plan_chunk : 4;
+    plan->waves_per_cu = ctx->plan_valid ? ctx->plan_waves_per_cu : 8;
+    plan->ms = 0.0f;
+    return RBF_OK;
+}
+
+// Plan search: every (chunk, waves per CU) candidate runs the whole batch once
+// (after one warm-up run) and is timed with HIP events on the context stream;
+// the fastest becomes the context's plan.  This call synchronises.  With a
+// cache path, a plan stored there for the same device and batch signature is
+// reused without timing, and a newly tuned plan is appended.
+extern "C" rbf_status rbf_autotune_batched(rbf_ctx* ctx, const rbf_domain_desc* doms, int n_doms,
+                                           const rbf_options* opt, void* workspace, size_t ws_bytes,
+                                           const char* cache_path, rbf_plan* best_out) {
+    if (!ctx) return RBF_EINVAL;
+    rbf_options o;
+    rbf_options_default(&o);
+    if (opt) o = *opt;
+    int64_t total = 0;
+    rbf_status st = rbf::check_doms(doms, n_doms, &total);
+    if (st != RBF_OK) return st;
+    RBF_HIP_CHECK(hipSetDevice(ctx->device));
+    hipDeviceProp_t prop;
+    RBF_HIP_CHECK(hipGetDeviceProperties(&prop, ctx->device));
+    // batch signature: device, precision, domain sizes and shapes
+    std::string key = std::string(prop.gcnArchName) + "|p" + std::to_string(o.precision);
+    for (int k = 0; k < n_doms; ++k)
+        key += "|" + std::to_string(doms[k].d) + ":" + std::to_string(doms[k].N) + ":" + std::to_string(doms[k].nnz) +
+               ":" + std::to_string(doms[k].degree ? -1 : doms[k].degree_uniform) + ":" + std::to_string(doms[k].n_max);
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "r");
+        if (f) {
+            char line[1024];
+            while (fgets(line, sizeof(line), f)) {
+                char k[900];
+                int c = 0, w = 0;
+                float ms = 0;
+                if (sscanf(line, "%899s %d %d %f", k, &c, &w, &ms) == 4 && key == k && c >= 1 && w >= 1) {
+                    fclose(f);
+                    rbf_plan p{c, w, ms};
+                    rbf_set_plan(ctx, &p);
+                    if (best_out) *best_out = p;
+                    return RBF_OK;
+                }
+            }
+            fclose(f);
+        }
+    }
+    const int chunks[] = {1, 2, 4, 8, 16};
+    const int waves[] = {4, 8, 12, 16};
+    hipEvent_t e0, e1;
+    RBF_HIP_CHECK(hipEventCreate(&e0));
+    RBF_HIP_CHECK(hipEventCreate(&e1));
+    rbf_plan best{4, 8, 1e30f};
+    st = rbf::run_batched(ctx, doms, n_doms, o, workspace, ws_bytes, 4, 8);  // warm-up
+    if (st == RBF_OK) {
+        for (int c : chunks)
+            for (int w : waves) {
+                if (hipEventRecord(e0, ctx->stream) != hipSuccess) { st = RBF_EHIP; break; }
+                st = rbf::run_batched(ctx, doms, n_doms, o, workspace, ws_bytes, c, w);
+                if (st != RBF_OK) break;
+                if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                    st = RBF_EHIP;
+                    break;
+                }
+                float ms = 0;
+                if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = RBF_EHIP; break; }
+                if (ms < best.ms) best = rbf_plan{c, w, ms};
+            }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != RBF_OK) return st;
+    rbf_set_plan(ctx, &best);
+    if (best_out) *best_out = best;
+    if (cache_path) {
+        FILE* f = fopen(cache_path, "a");
+        if (f) {
+            fprintf(f, "%s %d %d %.4f\n", key.c_str(), best.chunk, best.waves_per_cu, best.ms);
+            fclose(f);
+        }
+    }
+    return RBF_OK;
+}

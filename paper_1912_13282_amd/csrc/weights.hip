@@ -15,14 +15,19 @@ static std::vector<ClassEntry>& registry() {
 
 void register_class(const ClassEntry& e) { registry().push_back(e); }
 
-const ClassEntry* find_class(int d, int P, int M) {
+const ClassEntry* find_class(int M) {
     const ClassEntry* best = nullptr;
     for (const auto& c : registry())
-        if (c.d == d && c.P == P && c.maxm >= M && (!best || c.maxm < best->maxm)) best = &c;
+        if (c.maxm >= M && (!best || c.maxm < best->maxm)) best = &c;
     return best;
 }
 
 }  // namespace rbf
+
+__global__ __launch_bounds__(256) void k_mark_fallback(int8_t* __restrict__ status, int64_t N) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N && status[i] == RBF_ST_OK) status[i] = RBF_ST_FALLBACK;
+}
 
 extern "C" rbf_status rbf_options_default(rbf_options* opt) {
     if (!opt) return RBF_EINVAL;
@@ -51,12 +56,16 @@ extern "C" rbf_status rbf_compute_weights(rbf_ctx* ctx, const double* X, int64_t
     if (o.precision == RBF_PREC_F32_IR && !status) return RBF_EINVAL;  // the fallback list lives in status
     if (o.max_refine < 0 || o.scale_mode < 0 || o.scale_mode > 1 || !(o.refine_tol >= 0.0)) return RBF_EINVAL;
     const int m = n_mono(d, degree);
-    const rbf::ClassEntry* c = rbf::find_class(d, degree, n_max + m);
+    const rbf::ClassEntry* c = rbf::find_class(n_max + m);
     if (!c) return RBF_EUNSUPPORTED;
+    // the refined form exists for systems up to 64 unknowns; larger ones are solved in float64
+    const int prec = (c->maxm > 64) ? RBF_PREC_F64 : o.precision;
     RBF_HIP_CHECK(hipSetDevice(ctx->device));
     rbf::StencilArgs a;
     a.X = X;
     a.N = N;
+    a.d = d;
+    a.P = degree;
     a.offsets = offsets;
     a.idx = idx;
     a.nnz = nnz;
@@ -67,6 +76,11 @@ extern "C" rbf_status rbf_compute_weights(rbf_ctx* ctx, const double* X, int64_t
     a.repro_tol = o.repro_tol;
     a.w = w;
     a.status = status;
-    if (c->fn(a, N, o.precision, o.max_refine, o.refine_tol, ctx->stream) != hipSuccess) return RBF_EHIP;
+    if (c->fn(a, N, prec, o.max_refine, o.refine_tol, ctx->stream) != hipSuccess) return RBF_EHIP;
+    if (prec != o.precision) {
+        // mark every valid stencil of the float64 solve as FALLBACK (float64 used)
+        hipLaunchKernelGGL(k_mark_fallback, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, ctx->stream, status, N);
+        RBF_LAUNCH_CHECK();
+    }
     return RBF_OK;
 }

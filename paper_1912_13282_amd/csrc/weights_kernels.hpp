@@ -1,82 +1,72 @@
 // Kernels of the RBF-FD weight computation and their per-size-class registry.
-// Every (dimension, degree, system-size class) is instantiated in a translation
-// unit of its own (wcls_*.hip) so that the heavily unrolled classes compile in
-// parallel; each registers its launcher at load time.
+// A class is the register-array size MAXM (system size n + m <= MAXM); every
+// class is instantiated in a translation unit of its own (wcls_*.hip) so the
+// unrolled solvers compile in parallel, and registers its launcher at load time.
 #pragma once
 
-#include "weights_f64.hpp"
-#include "weights_ir.hpp"
-#include "weights_gj.hpp"
-#include "weights_irgj.hpp"
+#include "wsolve.hpp"
 
 namespace rbf {
 
 template <int MAXM>
 constexpr int waves_per_block() { return MAXM <= 64 ? 4 : 1; }
 
+template <int MAXM>
+constexpr int row_lds_doubles() {
+    if constexpr (MAXM <= 64) return RowLds<MAXM>::TOTAL;
+    else return big_lds_doubles<MAXM>();
+}
+
 // Plain FP64 solve.  With fallback_pass set, only stencils whose status is
 // FALLBACK (left by the refined form) are solved; they keep status FALLBACK.
-template <int D, int P, int MAXM>
-__device__ __forceinline__ void stencil_f64_any(const StencilArgs& a, int64_t node, double* lds) {
-    if constexpr (MAXM <= 64) stencil_f64_gj<D, P, MAXM>(a, node, lds);
-    else stencil_f64<D, P, MAXM>(a, node, lds);
-}
-
-template <int D, int P, int MAXM>
-constexpr int f64_lds_doubles() {
-    return MAXM <= 64 ? GjLds<D, P, MAXM>::TOTAL : n_mono(D, P) * (MAXM - n_mono(D, P));
-}
-
-template <int D, int P, int MAXM>
-__global__ __launch_bounds__(MAXM <= 64 ? 256 : 64, MAXM <= 64 ? 3 : 1) void k_weights_f64(StencilArgs a, int64_t N, int fallback_pass) {
+template <int MAXM>
+__global__ __launch_bounds__(MAXM <= 64 ? 256 : 64, MAXM <= 64 ? 3 : 1) void k_weights_f64(StencilArgs a, int64_t N,
+                                                                                        int fallback_pass) {
     constexpr int WPB = waves_per_block<MAXM>();
-    __shared__ __attribute__((aligned(16))) double lds[WPB][f64_lds_doubles<D, P, MAXM>()];
+    __shared__ __attribute__((aligned(16))) double lds[WPB][row_lds_doubles<MAXM>()];
     const int wv = threadIdx.x / WAVE;
     const int64_t node = (int64_t)blockIdx.x * WPB + wv;
     if (node >= N) return;
-    // one body for both uses (a second call site would duplicate the unrolled code)
+    // one call site: a second one would duplicate the unrolled solver
     if (fallback_pass && a.status[node] != RBF_ST_FALLBACK) return;
-    stencil_f64_any<D, P, MAXM>(a, node, lds[wv]);
+    if constexpr (MAXM <= 64) stencil_f64_rows<MAXM, false>(a, node, a.P, lds[wv]);
+    else stencil_f64_big<MAXM>(a, node, a.P, lds[wv]);
     if (fallback_pass && lane_id() == 0 && a.status[node] == RBF_ST_OK) a.status[node] = RBF_ST_FALLBACK;
 }
 
-// FP32 LU + FP64 refinement; stencils not accepted are marked FALLBACK.
-template <int D, int P, int MAXM>
-constexpr int ir_lds_doubles() {
-    if constexpr (MAXM <= 64) return IrLds<D, P, MAXM>::TOTAL;
-    else return 2;
-}
-
-template <int D, int P, int MAXM>
-__global__ __launch_bounds__(MAXM <= 64 ? 256 : 64, MAXM <= 64 ? 3 : 1) void k_weights_ir(StencilArgs a, int64_t N, int max_refine,
-                                                                      double refine_tol) {
-    constexpr int WPB = waves_per_block<MAXM>();
-    __shared__ __attribute__((aligned(16))) double lds[WPB][ir_lds_doubles<D, P, MAXM>()];
+// FP32 Gauss-Jordan + FP64 refinement; stencils not accepted are marked FALLBACK.
+template <int MAXM>
+__global__ __launch_bounds__(256, 3) void k_weights_ir(StencilArgs a, int64_t N, int max_refine, double refine_tol) {
+    static_assert(MAXM <= 64, "the refined form keeps one row per lane");
+    __shared__ __attribute__((aligned(16))) double lds[4][RowLds<MAXM>::TOTAL];
     const int wv = threadIdx.x / WAVE;
-    const int64_t node = (int64_t)blockIdx.x * WPB + wv;
+    const int64_t node = (int64_t)blockIdx.x * 4 + wv;
     if (node >= N) return;
-    if constexpr (MAXM <= 64) stencil_ir_gj<D, P, MAXM>(a, node, lds[wv], max_refine, refine_tol);
+    stencil_ir_rows<MAXM, false>(a, node, a.P, lds[wv], max_refine, refine_tol);
 }
 
 using LaunchFn = hipError_t (*)(const StencilArgs&, int64_t, int, int, double, hipStream_t);
 
-template <int D, int P, int MAXM>
+template <int MAXM>
 hipError_t launch_class(const StencilArgs& a, int64_t N, int precision, int max_refine, double refine_tol,
                         hipStream_t s) {
     constexpr int WPB = waves_per_block<MAXM>();
-    dim3 grid((unsigned)((N + WPB - 1) / WPB)), block(64 * WPB);
-    if (precision == RBF_PREC_F64 || MAXM > 64) {
-        // the refined form keeps FP64 rows in registers and exists for n + m <= 64 only
-        hipLaunchKernelGGL((k_weights_f64<D, P, MAXM>), grid, block, 0, s, a, N, 0);
+    const dim3 grid((unsigned)((N + WPB - 1) / WPB)), block(64 * WPB);
+    if constexpr (MAXM > 64) {
+        // systems above 64 unknowns are solved in float64 directly; the refined
+        // form reports them as FALLBACK (float64 used)
+        hipLaunchKernelGGL((k_weights_f64<MAXM>), grid, block, 0, s, a, N, 0);
+    } else if (precision == RBF_PREC_F64) {
+        hipLaunchKernelGGL((k_weights_f64<MAXM>), grid, block, 0, s, a, N, 0);
     } else {
-        hipLaunchKernelGGL((k_weights_ir<D, P, MAXM>), grid, block, 0, s, a, N, max_refine, refine_tol);
-        hipLaunchKernelGGL((k_weights_f64<D, P, MAXM>), grid, block, 0, s, a, N, 1);
+        hipLaunchKernelGGL((k_weights_ir<MAXM>), grid, block, 0, s, a, N, max_refine, refine_tol);
+        hipLaunchKernelGGL((k_weights_f64<MAXM>), grid, block, 0, s, a, N, 1);
     }
     return hipGetLastError();
 }
 
 struct ClassEntry {
-    int d, P, maxm;
+    int maxm;
     LaunchFn fn;
 };
 
@@ -89,7 +79,7 @@ struct ClassRegistrar {
 
 }  // namespace rbf
 
-#define RBF_WEIGHTS_CLASS(D, P, MX)                                                                  \
-    namespace {                                                                                      \
-    const rbf::ClassRegistrar rbf_reg_##D##_##P##_##MX(rbf::ClassEntry{D, P, MX, &rbf::launch_class<D, P, MX>}); \
+#define RBF_WEIGHTS_CLASS(MX) \
+    namespace {               \
+    const rbf::ClassRegistrar rbf_reg_##MX(rbf::ClassEntry{MX, &rbf::launch_class<MX>}); \
     }

@@ -1,0 +1,105 @@
+"""GPU parity of the batched persistent form (mixed dimension, per-node degree and
+stencil size, one launch) and of large systems (n + m up to 128), against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import nodesets as ns
+import paper_1912_13282_amd as rb
+from oracle import knn as oknn
+from oracle import rbffd as orbf
+
+pytestmark = pytest.mark.gpu
+
+ORD = {"lap": 2, "dx": 1, "dy": 1, "dz": 1}
+
+
+def scaled_err(wg, wo, ops, off, h):
+    hn = np.repeat(h, np.diff(off))
+    worst = 0.0
+    for r, op in enumerate(ops):
+        sc = hn ** ORD[op]
+        den = max(1.0, float(np.max(np.abs(wo[r]) * sc)))
+        worst = max(worst, float(np.max(np.abs(wg[r] - wo[r]) * sc)) / den)
+    return worst
+
+
+def build_batch(dev, per_domain=1500, seed=1003):
+    """The four mixed-batch domains at a reduced size (same recipe as the 8M-node batch)."""
+    doms, ref = [], []
+    for nd, P, n in ns.mixed_domains(per_domain, seed):
+        off = ns.offsets_from_sizes(n)
+        Xd = torch.from_numpy(nd.X).to(dev)
+        od = torch.from_numpy(off).to(dev)
+        idx = rb.select_stencils(Xd, od, int(n.max()))
+        ops = ("lap", "dx", "dy") + (("dz",) if nd.d == 3 else ())
+        D = rb.Domain(Xd, od, idx, int(n.max()), torch.from_numpy(P).to(dev), ops)
+        doms.append(D)
+        ref.append((nd, P, off, ops))
+    torch.cuda.synchronize()
+    return doms, ref
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32_ir"])
+def test_batched_mixed_parity(gpu, precision):
+    doms, ref = build_batch(gpu)
+    rb.compute_weights_batched(doms, precision=precision)
+    torch.cuda.synchronize()
+    for D, (nd, P, off, ops) in zip(doms, ref):
+        idx = D.idx.cpu().numpy()
+        o2, i2 = oknn.knn_exact(nd.X, np.diff(off))
+        assert np.array_equal(idx, i2), nd.meta["domain"]
+        wo, sto = orbf.weights(nd.X, off, idx, P.astype(np.int64), ops)
+        st = D.status.cpu().numpy()
+        assert sto.min() == 0
+        if precision == "f64":
+            assert np.all(st == 0), np.unique(st, return_counts=True)
+            tol = 1e-10
+        else:
+            assert np.all((st == 1) | (st == 2)), np.unique(st, return_counts=True)
+            tol = 1e-9
+        E = scaled_err(D.w.cpu().numpy(), wo, ops, off, nd.h)
+        print(f"  {nd.meta['domain']} {precision} E = {E:.2e} status {np.unique(st, return_counts=True)}", flush=True)
+        assert E <= tol
+
+
+def test_autotune_plan_and_cache(gpu, tmp_path):
+    doms, ref = build_batch(gpu, per_domain=600)
+    cache = str(tmp_path / "plans.txt")
+    plan = rb.autotune_batched(doms, precision="f64", cache_path=cache)
+    assert plan["chunk"] >= 1 and plan["waves_per_cu"] >= 1 and plan["ms"] > 0
+    assert rb.get_plan() == {"chunk": plan["chunk"], "waves_per_cu": plan["waves_per_cu"]}
+    w1 = [D.w.clone() for D in doms]
+    rb.set_plan(None)
+    plan2 = rb.autotune_batched(doms, precision="f64", cache_path=cache)   # served from the cache
+    assert (plan2["chunk"], plan2["waves_per_cu"]) == (plan["chunk"], plan["waves_per_cu"])
+    rb.compute_weights_batched(doms, precision="f64")
+    for a, D in zip(w1, doms):
+        assert torch.equal(a, D.w)        # plans change scheduling, never results
+    rb.set_plan(1, 4)
+    rb.compute_weights_batched(doms, precision="f64")
+    for a, D in zip(w1, doms):
+        assert torch.equal(a, D.w)
+    rb.set_plan(None)
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32_ir"])
+def test_large_systems_parity(gpu, precision):
+    """n = 65, degree 4 in 3D (m = 35, n + m = 100): the large-3D workload's stencil shape."""
+    C, R = ns.random_balls(1005, count=8)
+    nd = ns.cube_minus_balls(1.0 / 14, 1006, C, R)
+    off = ns.offsets_from_sizes(np.full(nd.N, 65, np.int64))
+    Xd, od = torch.from_numpy(nd.X).to(gpu), torch.from_numpy(off).to(gpu)
+    idx = rb.select_stencils(Xd, od, 65)
+    ops = ("lap", "dx", "dy", "dz")
+    w, st = rb.compute_weights(Xd, od, idx, 65, 4, ops, precision=precision)
+    torch.cuda.synchronize()
+    idx = idx.cpu().numpy()
+    o2, i2 = oknn.knn_exact(nd.X, 65)
+    assert np.array_equal(idx, i2)
+    wo, sto = orbf.weights(nd.X, off, idx, 4, ops)
+    st = st.cpu().numpy()
+    assert np.all(st == (0 if precision == "f64" else 2))
+    E = scaled_err(w.cpu().numpy(), wo, ops, off, nd.h)
+    print(f"  N={nd.N} E={E:.2e}", flush=True)
+    assert E <= 1e-10
