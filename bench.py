@@ -58,7 +58,47 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="time only the reported form")
     ap.add_argument("--cpu-sample", type=int, default=30000)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the timed steps, run a plain 1 GiB read + 1 GiB write elementwise kernel "
+                         "(torch.neg on float64) three times, the reference for HBM byte counters")
     return ap.parse_args()
+
+
+# Kernel sources of the weights path; the HBM traffic recorded under profiles/
+# belongs to the build whose sources hash to the recorded value.
+WEIGHTS_SOURCES = ("include/rbffd.h", "paper_1912_13282_amd/csrc/common.hpp", "paper_1912_13282_amd/csrc/wsolve.hpp",
+                   "paper_1912_13282_amd/csrc/weights_kernels.hpp", "paper_1912_13282_amd/csrc/weights.hip",
+                   "paper_1912_13282_amd/csrc/wcls_56.hip")
+TRAFFIC_FILE = "profiles/traffic_weights_cube_minus_sphere_3d.txt"
+
+
+def weights_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in WEIGHTS_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(form: str):
+    """HBM bytes per launch of the dominant weights kernel from the committed
+    FETCH_SIZE / WRITE_SIZE passes, or None if absent or taken on other sources."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_hash") != weights_source_hash() or kv.get("form") != form:
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def main():
@@ -152,7 +192,7 @@ def main():
     t_w = main_r["phases_ms"]["compute_weights"] / 1000.0
     achieved = flop * N / t_w / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": recorded_traffic(a.form),
                 "kernel": "k_weights_ir + k_weights_f64(fallback pass)" if a.form == "f32_ir" else "k_weights_f64",
                 "flop_per_stencil": flop, "stencils_per_launch": N}
     phases_roofline = {
@@ -179,6 +219,16 @@ def main():
     if "f64" in results and "f32_ir" in results:
         out["mixed_vs_f64"] = results["f32_ir"]["knn_weights_stencils_per_s"] / results["f64"]["knn_weights_stencils_per_s"]
 
+    if a.calib_copy:
+        src = torch.randn(1 << 27, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: 3 x (read {src.numel() * 8} B + write {dst.numel() * 8} B)",
+              file=sys.stderr, flush=True)
+        del src, dst
+
     if not a.no_cpu:
         out["cpu_baseline"], out["error"] = cpu_baseline(nd, off, n, P, ops, weights_snapshot, a.cpu_sample)
     print(json.dumps(out), flush=True)
@@ -197,13 +247,16 @@ def cpu_baseline(nd, off, n, P, ops, snap, sample_size):
     sample = np.sort(rng.choice(nd.N, size=min(sample_size, nd.N), replace=False))
     with threadpool_limits(limits=1):
         t = time.perf_counter()
+        c0 = time.process_time()
         soff, sidx = oknn.knn_exact(nd.X, n, nodes=sample)
         Wo, _ = orbf.weights(nd.X, soff, sidx, P, ops)
         dt = time.perf_counter() - t
+        cpu_s = time.process_time() - c0
     st_idx = sidx.reshape(sample.size, n)
-    cpu = {"value": sample.size / dt, "unit": "stencils/s", "cores": 1, "kind": "oracle",
+    threads = max(1, int(round(cpu_s / dt)))   # threads the oracle kept busy on average
+    cpu = {"value": sample.size / dt, "unit": "stencils/s", "cores": threads, "kind": "oracle",
            "sample": f"{sample.size} seeded random nodes of the same workload (kNN against all {nd.N} nodes + weights), "
-                     f"{dt:.1f} s on one host core"}
+                     f"{dt:.1f} s wall, {cpu_s:.1f} s CPU, BLAS limited to one thread"}
     # error of each GPU form on the sample (C9-style scaled max-norm)
     err = {}
     h = nd.h[0]

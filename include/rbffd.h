@@ -76,9 +76,12 @@ typedef struct rbf_options {
     double refine_tol;   /* F32_IR acceptance: max|r| <= tol ||K|| max|x| per RHS with */
                          /* tol = max(sqrt(n+m) 2^-53, refine_tol); 0 (default) is    */
                          /* LAPACK dsgesv's test                                      */
+    double surrogate_tol;/* surrogate acceptance: reproduction residual <= tol        */
+                         /* (default 1e-6)                                            */
 } rbf_options;
 
-/* Default options (precision F64, 10 corrections, r^3, stencil-radius scale). */
+/* Default options (precision F64, 10 corrections, r^3, stencil-radius scale,
+ * reproduction tolerance 1e-8, surrogate tolerance 1e-6). */
 rbf_status rbf_options_default(rbf_options* opt);
 
 /* Human-readable text of a return code (static storage). */
@@ -190,6 +193,79 @@ rbf_status rbf_autotune_batched(rbf_ctx* ctx, const rbf_domain_desc* doms, int n
                                 const char* cache_path, rbf_plan* best);
 rbf_status rbf_set_plan(rbf_ctx* ctx, const rbf_plan* plan);   /* NULL: back to the default */
 rbf_status rbf_get_plan(const rbf_ctx* ctx, rbf_plan* plan);
+
+/* ------------------------------------------------------------------------ *
+ * Learned surrogate of the 2D, 15-node Laplacian weights (degree-2
+ * augmentation, m = 6).  Not part of the paper's method: a network replaces
+ * the local solve of eq. (rbf-system-aug) and its output is projected onto the
+ * second block row of that system (polynomial reproduction), which the plain
+ * weights satisfy exactly.
+ *
+ * Network: 30 -> 128 -> 128 -> 128 -> 15, exact-erf GELU after the hidden
+ * layers.  Input: the scaled offsets (x_j - x_i)/s, s = max_j |x_j - x_i|,
+ * in stencil order (x, y interleaved, the centre's zeros included), in the
+ * canonical frame of the stencil: rotated so that node 1 lies on +x, then
+ * y reflected so that node 2 has y >= 0 (float64, c = o_1x/|o_1|,
+ * s_ = o_1y/|o_1|, f = sign(c o_2y - s_ o_2x) (+1 at 0), x' = (c o_x + s_ o_y)/s,
+ * y' = f (c o_y - s_ o_x)/s, each operation rounded, no fused multiply-add,
+ * then rounded to float32).  Output: the scaled weights w_j s^2.  Parameters: one float32 array of
+ * RBF_MLP_NPARAM values, row-major W1[128][30], b1[128], W2[128][128], b2,
+ * W3[128][128], b3, W4[15][128], b4[15].  Products use bfloat16 operands and
+ * float32 accumulation; x, W and the hidden activations (forward) and the
+ * output and pre-activation gradients (backward) are rounded to bfloat16,
+ * round-to-nearest-even.  The "packed" array (RBF_MLP_PACKED_BYTES, caller
+ * owned, 16-byte aligned) holds the bfloat16 weights in the operand order of
+ * the kernels; it is derived from the parameters by rbf_mlp_pack and must be
+ * refreshed after every parameter change (rbf_mlp_adam does it).
+ * ------------------------------------------------------------------------ */
+#define RBF_MLP_NPARAM       38927
+#define RBF_MLP_PACKED_BYTES (148 * 1024)
+
+rbf_status rbf_mlp_pack(rbf_ctx* ctx, const float* params, void* packed);
+
+/* y[B][15] = network(x[B][30]) (float32 row-major). */
+rbf_status rbf_mlp_forward(rbf_ctx* ctx, const float* params, const void* packed,
+                           const float* x, int64_t B, float* y);
+
+/* Mean-squared-error loss over the batch, sum_{b,o} (y_bo - t_bo)^2 / (15 B),
+ * and its gradient with respect to every parameter (grads[RBF_MLP_NPARAM]).
+ * x[n_rows][30], t[n_rows][15]; the batch rows are sel[0..B) (sel may be NULL:
+ * rows 0..B-1, then B <= n_rows); a sel entry outside [0, n_rows) contributes
+ * nothing.  loss (device float, may be NULL).  Deterministic: per-block partial
+ * sums reduced in a fixed order.  Workspace: rbf_mlp_grad_workspace. */
+rbf_status rbf_mlp_grad_workspace(int64_t B, size_t* bytes);
+rbf_status rbf_mlp_grad(rbf_ctx* ctx, const float* params, const void* packed,
+                        const float* x, const float* t, int64_t n_rows, const int64_t* sel, int64_t B,
+                        float* grads, float* loss, void* workspace, size_t ws_bytes);
+
+/* One Adam step (step = 1, 2, ...; bias-corrected moments m, v, float32) on
+ * params in place; packed (may be NULL) is refreshed from the new values. */
+rbf_status rbf_mlp_adam(rbf_ctx* ctx, float* params, const float* grads, float* m, float* v,
+                        int step, float lr, float beta1, float beta2, float eps, void* packed);
+
+/* Training pairs from 2D 15-node stencils: feat[N][30] (float32 scaled
+ * offsets), target[N][15] = w_lap * s^2 (may be NULL; w_lap the plain
+ * Laplacian weights [nnz] from rbf_compute_weights, or NULL), scale[N] = s
+ * (may be NULL).  Stencils of another size or with invalid indices get NaN rows. */
+rbf_status rbf_surrogate_dataset(rbf_ctx* ctx, const double* X, int64_t N,
+                                 const int64_t* offsets, const int32_t* idx, int64_t nnz,
+                                 const double* w_lap, float* feat, float* target, double* scale);
+
+/* Copy parameters (device float32 [RBF_MLP_NPARAM]) into the context and pack
+ * them; the context allocates its copy on the first call. */
+rbf_status rbf_surrogate_load(rbf_ctx* ctx, const float* params);
+
+/* Laplacian weights of 2D stencils through the loaded network: features,
+ * network, float64 projection w = y + Q (Q^T Q)^{-1} (l_q - Q^T y) onto the
+ * reproduction conditions, and the residual
+ * rho = max_l |(Q^T w - l_q)_l| / max(1, max |l_q|).  rho <= opt->surrogate_tol
+ * gives status RBF_ST_SURROGATE; otherwise (and for stencils that are not
+ * 15-node) the plain float64 solve runs and the status is
+ * RBF_ST_SURROGATE_REJECTED (or RBF_ST_SINGULAR / RBF_ST_BADSIZE from that
+ * solve).  w[nnz] float64, status[N] required.  n_max bounds every n_i. */
+rbf_status rbf_surrogate_weights(rbf_ctx* ctx, const double* X, int64_t N, int d,
+                                 const int64_t* offsets, const int32_t* idx, int64_t nnz,
+                                 int n_max, const rbf_options* opt, double* w, int8_t* status);
 
 #ifdef __cplusplus
 }

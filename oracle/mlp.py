@@ -101,11 +101,18 @@ def adam_step(params, grads, state, lr, b1=0.9, b2=0.999, eps=1e-8):
     return params
 
 
-def stencil_features(X, offsets, idx, nodes=None):
+def stencil_features(X, offsets, idx, nodes=None, canonical=False):
     """Inputs of the network: scaled offsets (x_j - x_i)/s in stencil order, flattened.
 
-    s = max_j ||x_j - x_i|| (the scaling of the weight computation).  Returns
-    (F [B, 2n] float64 interleaved x,y per node, s [B]).
+    s = max_j ||x_j - x_i|| (the scaling of the weight computation).  With
+    ``canonical`` the offsets are first expressed in the stencil's canonical
+    frame: rotated so that node 1 (the nearest neighbour) lies on +x, then
+    reflected in x so that node 2 has y >= 0.  The Laplacian weights of a
+    stencil do not change under rotations and reflections, so this loses
+    nothing.  Each operation is a separately rounded float64 operation:
+        c = o1x / |o1|, s_ = o1y / |o1|, f = -1 if c*o2y - s_*o2x < 0 else 1,
+        x' = (c*ox + s_*oy) / s,  y' = (f * (c*oy - s_*ox)) / s.
+    Returns (F [B, 2n] float64 interleaved x,y per node, s [B]).
     """
     X = np.asarray(X, dtype=np.float64)
     offsets = np.asarray(offsets, dtype=np.int64)
@@ -115,6 +122,17 @@ def stencil_features(X, offsets, idx, nodes=None):
     pos = offsets[nodes][:, None] + np.arange(n)[None, :]
     P = X[np.asarray(idx)[pos]]
     O = P - P[:, :1, :]
-    s = np.sqrt(np.sum(O * O, axis=-1)).max(axis=1)
-    Xh = O / s[:, None, None]
-    return Xh.reshape(len(nodes), -1), s
+    s = np.sqrt(O[:, :, 0] * O[:, :, 0] + O[:, :, 1] * O[:, :, 1]).max(axis=1)
+    if not canonical:
+        Xh = O / s[:, None, None]
+        return Xh.reshape(len(nodes), -1), s
+    o1x, o1y = O[:, 1, 0], O[:, 1, 1]
+    r = np.sqrt(o1x * o1x + o1y * o1y)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        c = np.where(r > 0, o1x / r, 1.0)
+        sn = np.where(r > 0, o1y / r, 0.0)
+    f = np.where(c * O[:, 2, 1] - sn * O[:, 2, 0] < 0, -1.0, 1.0)
+    ox, oy = O[:, :, 0], O[:, :, 1]
+    xr = (c[:, None] * ox + sn[:, None] * oy) / s[:, None]
+    yr = (f[:, None] * (c[:, None] * oy - sn[:, None] * ox)) / s[:, None]
+    return np.stack([xr, yr], axis=-1).reshape(len(nodes), -1), s

@@ -7,6 +7,9 @@ Python face of the HIP library ``librbffd.so`` (C ABI in include/rbffd.h):
     assemble_csr     -- the sparse operator in CSR form
     compute_weights_batched / autotune_batched
                      -- mixed 2D/3D, per-node degree and size in one persistent launch
+    mlp_* / surrogate_*
+                     -- the learned 2D Laplacian surrogate: MFMA forward/backward, Adam,
+                        projection onto the reproduction conditions, plain-solve fallback
 
 PyTorch supplies device memory and streams only.
 """
@@ -14,4 +17,6 @@ from ._binding import (  # noqa: F401
     OPS, ST_BADSIZE, ST_FALLBACK, ST_OK, ST_REFINED, ST_SINGULAR, ST_SURROGATE, ST_SURROGATE_REJECTED,
     Context, Domain, RbfError, assemble_csr, autotune_batched, compute_weights, compute_weights_batched, context,
     get_plan, lib, select_stencils, set_plan,
+    MLP_NPARAM, mlp_adam, mlp_flatten, mlp_forward, mlp_grad, mlp_pack, mlp_unflatten, surrogate_dataset,
+    surrogate_load, surrogate_weights,
 )

@@ -8,6 +8,7 @@ built, or a tensor is not on a GPU, the call raises.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import threading
 
@@ -33,7 +34,8 @@ class RbfError(RuntimeError):
 
 class rbf_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("max_refine", ctypes.c_int), ("phs_power", ctypes.c_int),
-                ("scale_mode", ctypes.c_int), ("repro_tol", ctypes.c_double), ("refine_tol", ctypes.c_double)]
+                ("scale_mode", ctypes.c_int), ("repro_tol", ctypes.c_double), ("refine_tol", ctypes.c_double),
+                ("surrogate_tol", ctypes.c_double)]
 
 
 class rbf_domain_desc(ctypes.Structure):
@@ -68,6 +70,14 @@ _SIGS = {
     "rbf_autotune_batched": [_P, ctypes.POINTER(rbf_domain_desc), _I, ctypes.POINTER(rbf_options), _P, _SZ,
                              ctypes.c_char_p, ctypes.POINTER(rbf_plan)],
     "rbf_set_plan": [_P, ctypes.POINTER(rbf_plan)],
+    "rbf_mlp_pack": [_P, _P, _P],
+    "rbf_mlp_forward": [_P, _P, _P, _P, _I64, _P],
+    "rbf_mlp_grad_workspace": [_I64, ctypes.POINTER(_SZ)],
+    "rbf_mlp_grad": [_P, _P, _P, _P, _P, _I64, _P, _I64, _P, _P, _P, _SZ],
+    "rbf_mlp_adam": [_P, _P, _P, _P, _P, _I, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _P],
+    "rbf_surrogate_dataset": [_P, _P, _I64, _P, _P, _I64, _P, _P, _P, _P],
+    "rbf_surrogate_load": [_P, _P],
+    "rbf_surrogate_weights": [_P, _P, _I64, _I, _P, _P, _I64, _I, ctypes.POINTER(rbf_options), _P, _P],
     "rbf_get_plan": [_P, ctypes.POINTER(rbf_plan)],
 }
 
@@ -139,7 +149,7 @@ def context(device=None) -> Context:
 
 
 def options(precision="f64", max_refine=10, phs_power=3, scale_mode=0, repro_tol=1e-8,
-            refine_tol=0.0) -> rbf_options:
+            refine_tol=0.0, surrogate_tol=1e-6) -> rbf_options:
     o = rbf_options()
     _check(lib().rbf_options_default(ctypes.byref(o)), "rbf_options_default")
     o.precision = PREC[precision]
@@ -148,6 +158,7 @@ def options(precision="f64", max_refine=10, phs_power=3, scale_mode=0, repro_tol
     o.scale_mode = int(scale_mode)
     o.repro_tol = float(repro_tol)
     o.refine_tol = float(refine_tol)
+    o.surrogate_tol = float(surrogate_tol)
     return o
 
 
@@ -324,3 +335,120 @@ def get_plan(ctx: Context | None = None, device=None):
     p = rbf_plan()
     _check(lib().rbf_get_plan(ctx._h, ctypes.byref(p)), "rbf_get_plan")
     return {"chunk": p.chunk, "waves_per_cu": p.waves_per_cu}
+
+
+# ------------------------------------------------------------------ surrogate
+MLP_NPARAM = 38927
+MLP_PACKED_BYTES = 148 * 1024
+MLP_SHAPES = (("W1", (128, 30)), ("b1", (128,)), ("W2", (128, 128)), ("b2", (128,)),
+              ("W3", (128, 128)), ("b3", (128,)), ("W4", (15, 128)), ("b4", (15,)))
+
+
+def mlp_flatten(params: dict) -> torch.Tensor:
+    """Parameter dict (W1..W4 [out, in], b1..b4) -> the flat float32 layout of the library."""
+    return torch.cat([torch.as_tensor(params[k]).reshape(-1).to(torch.float32) for k, _ in MLP_SHAPES])
+
+
+def mlp_unflatten(flat) -> dict:
+    flat = torch.as_tensor(flat)
+    out, o = {}, 0
+    for k, shp in MLP_SHAPES:
+        n = math.prod(shp)
+        out[k] = flat[o:o + n].reshape(shp)
+        o += n
+    return out
+
+
+def _f32(t, name):
+    return _dev(t, torch.float32, name)
+
+
+def mlp_pack(params: torch.Tensor, packed: torch.Tensor | None = None, ctx: Context | None = None):
+    ctx = ctx or context(params.device)
+    if packed is None:
+        packed = torch.empty(MLP_PACKED_BYTES, dtype=torch.uint8, device=params.device)
+    _check(lib().rbf_mlp_pack(ctx._sync_stream(), _f32(params, "params"), _dev(packed, torch.uint8, "packed")),
+           "rbf_mlp_pack")
+    return packed
+
+
+def mlp_forward(params, packed, x, y=None, ctx: Context | None = None):
+    ctx = ctx or context(params.device)
+    B = x.shape[0]
+    if y is None:
+        y = torch.empty((B, 15), dtype=torch.float32, device=x.device)
+    _check(lib().rbf_mlp_forward(ctx._sync_stream(), _f32(params, "params"), _dev(packed, torch.uint8, "packed"),
+                                 _f32(x, "x"), B, _f32(y, "y")), "rbf_mlp_forward")
+    return y
+
+
+def mlp_grad_workspace(B: int) -> int:
+    b = _SZ()
+    _check(lib().rbf_mlp_grad_workspace(int(B), ctypes.byref(b)), "rbf_mlp_grad_workspace")
+    return b.value
+
+
+def mlp_grad(params, packed, x, t, sel=None, B=None, grads=None, loss=None, workspace=None, ctx: Context | None = None):
+    """Gradients of the mean-squared error over rows sel (or all rows) of x, t."""
+    ctx = ctx or context(params.device)
+    if x.dim() != 2 or t.dim() != 2 or x.shape[1] != 30 or t.shape[1] != 15 or t.shape[0] != x.shape[0]:
+        raise ValueError("x must be [rows, 30] and t [rows, 15]")
+    B = int(sel.numel() if sel is not None else (B if B is not None else x.shape[0]))
+    if grads is None:
+        grads = torch.empty(MLP_NPARAM, dtype=torch.float32, device=params.device)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=params.device)
+    nb = mlp_grad_workspace(B)
+    if workspace is None or workspace.numel() < nb:
+        workspace = torch.empty(nb, dtype=torch.uint8, device=params.device)
+    _check(lib().rbf_mlp_grad(ctx._sync_stream(), _f32(params, "params"), _dev(packed, torch.uint8, "packed"),
+                              _f32(x, "x"), _f32(t, "t"), x.shape[0],
+                              _dev(sel, torch.int64, "sel") if sel is not None else None, B,
+                              _f32(grads, "grads"), _f32(loss, "loss"), _dev(workspace, torch.uint8, "workspace"),
+                              workspace.numel()), "rbf_mlp_grad")
+    return grads, loss
+
+
+def mlp_adam(params, grads, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8, packed=None, ctx: Context | None = None):
+    ctx = ctx or context(params.device)
+    _check(lib().rbf_mlp_adam(ctx._sync_stream(), _f32(params, "params"), _f32(grads, "grads"), _f32(m, "m"),
+                              _f32(v, "v"), int(step), float(lr), float(beta1), float(beta2), float(eps),
+                              _dev(packed, torch.uint8, "packed") if packed is not None else None), "rbf_mlp_adam")
+
+
+def surrogate_dataset(X, offsets, idx, w_lap=None, ctx: Context | None = None):
+    """(features [N,30] f32, targets [N,15] f32 or None, scale [N] f64) of 2D 15-node stencils."""
+    ctx = ctx or context(X.device)
+    N = X.shape[0]
+    feat = torch.empty((N, 30), dtype=torch.float32, device=X.device)
+    tgt = torch.empty((N, 15), dtype=torch.float32, device=X.device) if w_lap is not None else None
+    scale = torch.empty(N, dtype=torch.float64, device=X.device)
+    _check(lib().rbf_surrogate_dataset(ctx._sync_stream(), _dev(X, torch.float64, "X"), N,
+                                       _dev(offsets, torch.int64, "offsets"), _dev(idx, torch.int32, "idx"),
+                                       idx.numel(),
+                                       _dev(w_lap, torch.float64, "w_lap") if w_lap is not None else None,
+                                       _f32(feat, "feat"), _f32(tgt, "target") if tgt is not None else None,
+                                       _dev(scale, torch.float64, "scale")), "rbf_surrogate_dataset")
+    return feat, tgt, scale
+
+
+def surrogate_load(params, ctx: Context | None = None):
+    ctx = ctx or context(params.device)
+    _check(lib().rbf_surrogate_load(ctx._sync_stream(), _f32(params, "params")), "rbf_surrogate_load")
+
+
+def surrogate_weights(X, offsets, idx, n_max, w=None, status=None, ctx: Context | None = None, **opt):
+    """Laplacian weights through the loaded network + projection, plain solve where rejected."""
+    ctx = ctx or context(X.device)
+    N, d = X.shape
+    nnz = idx.numel()
+    if w is None:
+        w = torch.empty(nnz, dtype=torch.float64, device=X.device)
+    if status is None:
+        status = torch.empty(N, dtype=torch.int8, device=X.device)
+    o = options(**opt)
+    _check(lib().rbf_surrogate_weights(ctx._sync_stream(), _dev(X, torch.float64, "X"), N, d,
+                                       _dev(offsets, torch.int64, "offsets"), _dev(idx, torch.int32, "idx"), nnz,
+                                       int(n_max), ctypes.byref(o), _dev(w, torch.float64, "w"),
+                                       _dev(status, torch.int8, "status")), "rbf_surrogate_weights")
+    return w, status

@@ -37,6 +37,7 @@ extern "C" rbf_status rbf_options_default(rbf_options* opt) {
     opt->scale_mode = 0;
     opt->repro_tol = 1e-8;
     opt->refine_tol = 0.0;
+    opt->surrogate_tol = 1e-6;
     return RBF_OK;
 }
 

@@ -17,21 +17,22 @@ constexpr int row_lds_doubles() {
     else return big_lds_doubles<MAXM>();
 }
 
-// Plain FP64 solve.  With fallback_pass set, only stencils whose status is
-// FALLBACK (left by the refined form) are solved; they keep status FALLBACK.
+// Plain FP64 solve.  With select != 0 only the stencils whose status equals
+// select (FALLBACK left by the refined form, SURROGATE_REJECTED left by the
+// surrogate) are solved, and a successful solve keeps that status.
 template <int MAXM>
 __global__ __launch_bounds__(MAXM <= 64 ? 256 : 64, MAXM <= 64 ? 3 : 1) void k_weights_f64(StencilArgs a, int64_t N,
-                                                                                        int fallback_pass) {
+                                                                                        int select) {
     constexpr int WPB = waves_per_block<MAXM>();
     __shared__ __attribute__((aligned(16))) double lds[WPB][row_lds_doubles<MAXM>()];
     const int wv = threadIdx.x / WAVE;
     const int64_t node = (int64_t)blockIdx.x * WPB + wv;
     if (node >= N) return;
     // one call site: a second one would duplicate the unrolled solver
-    if (fallback_pass && a.status[node] != RBF_ST_FALLBACK) return;
+    if (select && a.status[node] != select) return;
     if constexpr (MAXM <= 64) stencil_f64_rows<MAXM, false>(a, node, a.P, lds[wv]);
     else stencil_f64_big<MAXM>(a, node, a.P, lds[wv]);
-    if (fallback_pass && lane_id() == 0 && a.status[node] == RBF_ST_OK) a.status[node] = RBF_ST_FALLBACK;
+    if (select && lane_id() == 0 && a.status[node] == RBF_ST_OK) a.status[node] = (int8_t)select;
 }
 
 // FP32 Gauss-Jordan + FP64 refinement; stencils not accepted are marked FALLBACK.
@@ -60,18 +61,32 @@ hipError_t launch_class(const StencilArgs& a, int64_t N, int precision, int max_
         hipLaunchKernelGGL((k_weights_f64<MAXM>), grid, block, 0, s, a, N, 0);
     } else {
         hipLaunchKernelGGL((k_weights_ir<MAXM>), grid, block, 0, s, a, N, max_refine, refine_tol);
-        hipLaunchKernelGGL((k_weights_f64<MAXM>), grid, block, 0, s, a, N, 1);
+        hipLaunchKernelGGL((k_weights_f64<MAXM>), grid, block, 0, s, a, N, RBF_ST_FALLBACK);
     }
     return hipGetLastError();
 }
 
+// plain FP64 solve of the stencils whose status equals select
+template <int MAXM>
+hipError_t launch_select(const StencilArgs& a, int64_t N, int select, hipStream_t s) {
+    constexpr int WPB = waves_per_block<MAXM>();
+    hipLaunchKernelGGL((k_weights_f64<MAXM>), dim3((unsigned)((N + WPB - 1) / WPB)), dim3(64 * WPB), 0, s, a, N,
+                       select);
+    return hipGetLastError();
+}
+
+using SelectFn = hipError_t (*)(const StencilArgs&, int64_t, int, hipStream_t);
+
 struct ClassEntry {
     int maxm;
     LaunchFn fn;
+    SelectFn fallback;
 };
 
 // registry shared by all translation units (defined in weights.hip)
 void register_class(const ClassEntry& e);
+// smallest compiled class holding systems of M unknowns, or NULL
+const ClassEntry* find_class(int M);
 
 struct ClassRegistrar {
     explicit ClassRegistrar(const ClassEntry& e) { register_class(e); }
@@ -81,5 +96,5 @@ struct ClassRegistrar {
 
 #define RBF_WEIGHTS_CLASS(MX) \
     namespace {               \
-    const rbf::ClassRegistrar rbf_reg_##MX(rbf::ClassEntry{MX, &rbf::launch_class<MX>}); \
+    const rbf::ClassRegistrar rbf_reg_##MX(rbf::ClassEntry{MX, &rbf::launch_class<MX>, &rbf::launch_select<MX>}); \
     }

@@ -57,3 +57,53 @@ def test_host_argument_errors_without_gpu(lib_path):
     assert b.value > 1000 * (4 + 8 * 3)
     assert L.rbf_compute_weights(None, None, ctypes.c_int64(0), 2, None, None, ctypes.c_int64(0), 1, 2, 1,
                                  None, None, None) == -1
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C compiler's sizes and offsets."""
+    import ctypes
+    from paper_1912_13282_amd import _binding as B
+    src = tmp_path / "lay.c"
+    src.write_text(f'''#include <stdio.h>
+#include <stddef.h>
+#include "{HEADER}"
+#define F(T, f) printf(#T " " #f " %zu\\n", offsetof(T, f));
+int main(void) {{
+  printf("rbf_options size %zu\\n", sizeof(rbf_options));
+  F(rbf_options, precision) F(rbf_options, max_refine) F(rbf_options, phs_power) F(rbf_options, scale_mode)
+  F(rbf_options, repro_tol) F(rbf_options, refine_tol) F(rbf_options, surrogate_tol)
+  printf("rbf_domain_desc size %zu\\n", sizeof(rbf_domain_desc));
+  F(rbf_domain_desc, X) F(rbf_domain_desc, N) F(rbf_domain_desc, d) F(rbf_domain_desc, offsets)
+  F(rbf_domain_desc, idx) F(rbf_domain_desc, nnz) F(rbf_domain_desc, degree) F(rbf_domain_desc, degree_uniform)
+  F(rbf_domain_desc, n_max) F(rbf_domain_desc, op_mask) F(rbf_domain_desc, w) F(rbf_domain_desc, status)
+  printf("rbf_plan size %zu\\n", sizeof(rbf_plan));
+  F(rbf_plan, chunk) F(rbf_plan, waves_per_cu) F(rbf_plan, ms)
+  return 0;
+}}
+''')
+    exe = tmp_path / "lay"
+    subprocess.run(["gcc", "-O0", "-o", str(exe), str(src)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    py = {"rbf_options": B.rbf_options, "rbf_domain_desc": B.rbf_domain_desc, "rbf_plan": B.rbf_plan}
+    for line in filter(None, out):
+        T, f, v = line.split()
+        if f == "size":
+            assert ctypes.sizeof(py[T]) == int(v), T
+        else:
+            assert getattr(py[T], f).offset == int(v), (T, f)
+
+
+def test_mlp_parameter_layout():
+    """Flat parameter order W1, b1, ..., W4, b4 with the header's count."""
+    import torch
+    from paper_1912_13282_amd import _binding as B
+    src = open(HEADER).read()
+    assert int(re.search(r"#define RBF_MLP_NPARAM\s+(\d+)", src).group(1)) == B.MLP_NPARAM
+    shapes = dict(B.MLP_SHAPES)
+    assert sum(int(torch.tensor(s).prod()) for s in shapes.values()) == B.MLP_NPARAM
+    p = {k: torch.full(s, float(i)) for i, (k, s) in enumerate(B.MLP_SHAPES)}
+    flat = B.mlp_flatten(p)
+    back = B.mlp_unflatten(flat)
+    for k in p:
+        assert torch.equal(back[k], p[k])
+    assert flat[0] == 0 and flat[128 * 30] == 1 and flat[-1] == 7

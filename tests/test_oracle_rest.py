@@ -188,3 +188,27 @@ def test_poisson_convergence_rate(d, n, hs, slope_min):
         errs.append(err)
     slope = -np.polyfit(np.log(Ns), np.log(errs), 1)[0]
     assert slope >= slope_min * (2.0 / d), (Ns, errs, slope)
+
+
+def test_canonical_features_frame_and_invariance():
+    """Canonical inputs: node 1 on +x, node 2 in y >= 0, norms kept, and the same features
+    for a rotated and reflected copy of the node set (up to rounding)."""
+    nd = ns.disk(0.0404, 1001)
+    off, idx = knn.knn_exact(nd.X, 15)
+    nodes = np.arange(0, nd.N, 13)
+    F, s = mlp.stencil_features(nd.X, off, idx, nodes, canonical=True)
+    G, s0 = mlp.stencil_features(nd.X, off, idx, nodes, canonical=False)
+    F3, G3 = F.reshape(-1, 15, 2), G.reshape(-1, 15, 2)
+    assert np.array_equal(s, s0)
+    assert np.abs(F3[:, 1, 1]).max() <= 1e-15 and np.all(F3[:, 1, 0] > 0) and np.all(F3[:, 2, 1] >= -1e-15)
+    np.testing.assert_allclose(np.linalg.norm(F3, axis=-1), np.linalg.norm(G3, axis=-1), atol=1e-15)
+    th = 0.7
+    R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]]) @ np.diag([1.0, -1.0])
+    Fr, _ = mlp.stencil_features(nd.X @ R.T + 0.3, off, idx, nodes, canonical=True)
+    np.testing.assert_allclose(Fr, F, atol=1e-13)
+    # the Laplacian weights computed from the canonical coordinates are those of the stencil
+    Wt, _ = rbffd.weights(nd.X, off, idx, 2, ("lap",))
+    for k, i in enumerate(nodes[:20]):
+        Xs = F3[k] * s[k]
+        w2, _ = rbffd.weights(Xs, np.array([0, 15]), np.arange(15), 2, ("lap",))
+        np.testing.assert_allclose(w2[0], Wt[0, off[i]:off[i + 1]], rtol=1e-9, atol=1e-9 * np.abs(w2[0]).max())
