@@ -13,16 +13,22 @@ def lattice5():
 
 
 def test_lattice_ties_hand_derived():
+    """Hand-derived stencils of tests/golden/lattice_ties.txt (5x5 lattice, exact keys)."""
+    import os
     X = lattice5()
-    # centre 12 = (2,2); axis neighbours 7 (1,2), 11 (2,1), 13 (2,3), 17 (3,2): key 1
-    off, idx = knn.knn_bruteforce(X, 5)
-    assert idx[off[12]:off[13]].tolist() == [12, 7, 11, 13, 17]
-    # n = 12: 4 axis (key 1), 4 diagonals 6, 8, 16, 18 (key 2), then the lowest-index
-    # 3 of the 4 nodes at key 4: 2 (0,2), 10 (2,0), 14 (2,4) [22 (4,2) left out]
-    off, idx = knn.knn_bruteforce(X, 12)
-    assert idx[off[12]:off[13]].tolist() == [12, 7, 11, 13, 17, 6, 8, 16, 18, 2, 10, 14]
-    # corner 0 = (0,0), n = 4: 1 (0,1) and 5 (1,0) at key 1, then 6 (1,1) at key 2
-    assert knn.knn_bruteforce(X, 4)[1][0:4].tolist() == [0, 1, 5, 6]
+    cases = 0
+    with open(os.path.join(os.path.dirname(__file__), "golden", "lattice_ties.txt")) as f:
+        for line in f:
+            if not line.strip() or line.startswith("#"):
+                continue
+            head, st = line.split(":")
+            c, n = (int(t) for t in head.split())
+            off, idx = knn.knn_bruteforce(X, n)
+            assert idx[off[c]:off[c + 1]].tolist() == [int(t) for t in st.split()], line
+            off2, idx2 = knn.knn_exact(X, n)
+            assert np.array_equal(idx, idx2)
+            cases += 1
+    assert cases == 3
 
 
 def test_self_first_with_duplicate_node():

@@ -30,25 +30,40 @@ def jittered_stencil(d, n, rng, h=0.01):
 
 
 # ---------------------------------------------------------------- closed forms
+def golden_stars():
+    """Closed-form star weights from tests/golden/fd_stars.txt."""
+    import os
+    out = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "fd_stars.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                if k.endswith("offsets"):
+                    out[k] = np.array([[float(t) for t in p.split()] for p in v.split("|")])
+                else:
+                    out[k] = np.array([float(t) for t in v.split()])
+    return out
+
+
 @pytest.mark.parametrize("h", [1.0, 0.013, 3.7e-4])
 def test_unisolvent_2d_star(h):
+    g = golden_stars()
     c = np.array([0.31, -1.7])
-    Xs = c + h * np.array([[0, 0], [1, 0], [-1, 0], [0, 1], [0, -1], [1, 1]], float)
+    Xs = c + h * g["2d.offsets"]
     W = rbffd.stencil_weights(Xs, 2, ("lap", "dx", "dy"))
-    np.testing.assert_allclose(W[0] * h * h, [-4, 1, 1, 1, 1, 0], atol=1e-11)
-    np.testing.assert_allclose(W[1] * h, [0, 0.5, -0.5, 0, 0, 0], atol=1e-11)
-    np.testing.assert_allclose(W[2] * h, [0, 0, 0, 0.5, -0.5, 0], atol=1e-11)
+    np.testing.assert_allclose(W[0] * h * h, g["2d.lap_h2"], atol=1e-11)
+    np.testing.assert_allclose(W[1] * h, g["2d.dx_h"], atol=1e-11)
+    np.testing.assert_allclose(W[2] * h, g["2d.dy_h"], atol=1e-11)
 
 
 @pytest.mark.parametrize("phs", [3, 5])
 def test_unisolvent_3d_star(phs):
+    g = golden_stars()
     h = 0.02
-    E = np.eye(3)
-    Xs = h * np.array([np.zeros(3), E[0], -E[0], E[1], -E[1], E[2], -E[2],
-                       E[0] + E[1], E[0] + E[2], E[1] + E[2]])
+    Xs = h * g["3d.offsets"]
     W = rbffd.stencil_weights(Xs, 2, ("lap", "dz"), phs_power=phs)
-    np.testing.assert_allclose(W[0] * h * h, [-6, 1, 1, 1, 1, 1, 1, 0, 0, 0], atol=1e-10)
-    np.testing.assert_allclose(W[1] * h, [0, 0, 0, 0, 0, 0.5, -0.5, 0, 0, 0], atol=1e-10)
+    np.testing.assert_allclose(W[0] * h * h, g["3d.lap_h2"], atol=1e-10)
+    np.testing.assert_allclose(W[1] * h, g["3d.dz_h"], atol=1e-10)
 
 
 def test_monomial_count_and_order():
