@@ -1,19 +1,31 @@
 """Benchmark of the RBF-FD stencil hot path on one MI355X.
 
-One step = rbf_select_stencils + rbf_compute_weights + rbf_assemble_csr over the
-whole node set, inputs resident in HBM.  Default workload: [0,1]^3 minus the
-ball B((1/2,1/2,1/2), 0.3), jittered lattice h = 1/106 plus face lattice and
-Fibonacci sphere nodes (1,096,553 nodes), n = 35, degree 3 (m = 20), operators
-Laplacian, d/dx, d/dy, d/dz.  The reported form is FP32 LU + FP64 refinement;
-the plain FP64 form is timed beside it on the same inputs.
+Default workload (cube_sphere3d): [0,1]^3 minus the ball B((1/2,1/2,1/2), 0.3),
+jittered lattice h = 1/106 plus face lattice and Fibonacci sphere nodes
+(1,096,553 nodes), n = 35, degree 3 (m = 20), operators Laplacian, d/dx, d/dy,
+d/dz.  One step = rbf_select_stencils + rbf_compute_weights + rbf_assemble_csr
+over the whole node set, inputs resident in HBM.  The reported form is FP32 LU +
+FP64 refinement; the plain FP64 form is timed beside it on the same inputs.
 
-    python bench.py [--steps K] [--warmup W] [--form f32_ir|f64] [--no-cpu]
+Other workloads (the same JSON contract, one line each):
+  mixed    four 2D/3D domains (disk with holes, L-shape, cube minus sphere,
+           torus), 2M nodes each, per-node degree 2-4 and n in [12, 70]; the
+           weights of all four in one persistent launch per precision, plan
+           chosen by the autotuner before the timed steps
+  learned  the learned Laplacian surrogate: trained on the GPU on 5,000 seeded
+           disk node sets (10M stencils), timed on a 1.7M-node disk against the
+           plain FP64 and FP32+refinement solves; quality on the 2,007-node disk
+  large3d  [0,1]^3 minus 64 random balls, h = 1/256 (about 16M nodes), n = 65,
+           degree 4 (n + m = 100), with CSR
+
+    python bench.py [--workload W] [--steps K] [--warmup W] [--no-cpu] ...
 
 Prints one JSON line.  Only one GPU is supported: --gpus N with N > 1 exits.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -27,42 +39,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "RBF-FD stencils/s (kNN+weights) mixed/learned vs plain FP64 at stated error"
 PEAK_FP64_TFLOPS = 78.6     # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz (FMA, one lane op per clock)
+PEAK_BF16_TFLOPS = 2500.0   # dense bf16 MFMA
 PEAK_HBM_GBS = 8000.0
-OPS = ("lap", "dx", "dy", "dz")
-
-
-def weights_flops_per_stencil(n: int, m: int, d: int, R: int) -> float:
-    """Algorithmic FLOPs of one stencil's weights: LU of the (n+m)^2 system,
-    forward/back substitution of R right-hand sides, and the n^2 RBF entries
-    (d differences, d squares, d-1 additions, a square root and a product)."""
-    M = n + m
-    return (2.0 / 3.0) * M ** 3 + 2.0 * R * M * M + (3 * d + 1) * n * n
-
-
-def knn_bytes_per_stencil(n: int, d: int) -> float:
-    """Algorithmic HBM bytes of stencil selection: read the node, write n indices."""
-    return 8.0 * d + 4.0 * n
-
-
-def csr_bytes_per_stencil(n: int, R: int) -> float:
-    """Read idx and w, write col and vals, plus the row pointer."""
-    return 2.0 * (4.0 * n + 8.0 * R * n) + 8.0
-
-
-def parse():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--form", default="f32_ir", choices=["f32_ir", "f64"])
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-compare", action="store_true", help="time only the reported form")
-    ap.add_argument("--cpu-sample", type=int, default=30000)
-    ap.add_argument("--calib-copy", action="store_true",
-                    help="after the timed steps, run a plain 1 GiB read + 1 GiB write elementwise kernel "
-                         "(torch.neg on float64) three times, the reference for HBM byte counters")
-    return ap.parse_args()
-
+ORD = {"lap": 2, "dx": 1, "dy": 1, "dz": 1}
 
 # Kernel sources of the weights path; the HBM traffic recorded under profiles/
 # belongs to the build whose sources hash to the recorded value.
@@ -72,8 +51,29 @@ WEIGHTS_SOURCES = ("include/rbffd.h", "paper_1912_13282_amd/csrc/common.hpp", "p
 TRAFFIC_FILE = "profiles/traffic_weights_cube_minus_sphere_3d.txt"
 
 
+def weights_flops(n, m, d, R):
+    """Algorithmic FLOPs of one stencil's weights: LU of the (n+m)^2 system,
+    forward/back substitution of R right-hand sides, and the n^2 RBF entries
+    (d differences, d squares, d-1 additions, a square root and a product)."""
+    M = n + m
+    return (2.0 / 3.0) * M ** 3 + 2.0 * R * M * M + (3 * d + 1) * n * n
+
+
+def knn_bytes(n, d):
+    """Algorithmic HBM bytes of stencil selection: read the node, write n indices."""
+    return 8.0 * d + 4.0 * n
+
+
+def csr_bytes(n, R):
+    """Read idx and w, write col and vals, plus the row pointer."""
+    return 2.0 * (4.0 * n + 8.0 * R * n) + 8.0
+
+
+SURROGATE_FLOPS = 2.0 * (32 * 128 + 128 * 128 * 2 + 128 * 16)   # MFMA work per stencil (padded shapes)
+SURROGATE_BYTES = 8 + 15 * 4 + 15 * 8 + 1 + 16                  # offsets, idx, w, status, centre coordinates
+
+
 def weights_source_hash() -> str:
-    import hashlib
     h = hashlib.sha256()
     for f in WEIGHTS_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
@@ -101,6 +101,433 @@ def recorded_traffic(form: str):
         return None
 
 
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cube_sphere3d", choices=["cube_sphere3d", "mixed", "learned", "large3d"])
+    ap.add_argument("--form", default="f32_ir", choices=["f32_ir", "f64"])
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-compare", action="store_true", help="time only the reported form")
+    ap.add_argument("--cpu-sample", type=int, default=30000)
+    ap.add_argument("--per-domain", type=int, default=2_000_000, help="mixed: nodes per domain")
+    ap.add_argument("--train-sets", type=int, default=5000, help="learned: training node sets (2,008 nodes each)")
+    ap.add_argument("--train-epochs", type=int, default=8)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the timed steps, run a plain 1 GiB read + 1 GiB write elementwise kernel "
+                         "(torch.neg on float64) three times, the reference for HBM byte counters")
+    return ap.parse_args()
+
+
+class Timer:
+    """HIP events on the current stream (the stream every library call is enqueued on)."""
+
+    def __init__(self, torch, phases):
+        self.torch, self.phases = torch, phases
+        self.stream = torch.cuda.current_stream()
+
+    def run(self, step, K, W):
+        torch = self.torch
+        for _ in range(W):
+            step(None)
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(self.phases) + 1)] for _ in range(K)]
+        t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter()
+        t0.record(self.stream)
+        for k in range(K):
+            step(evs[k])
+        t1.record(self.stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall
+        ph = np.array([[e[j].elapsed_time(e[j + 1]) for j in range(len(self.phases))] for e in evs])
+        return t0.elapsed_time(t1) / K, 1000.0 * wall / K, dict(zip(self.phases, ph.mean(axis=0).tolist()))
+
+
+def scaled_err(wg, wo, ops, hn):
+    worst = 0.0
+    for c, op in enumerate(ops):
+        sc = hn ** ORD[op]
+        den = max(1.0, float(np.max(np.abs(wo[c]) * sc)))
+        worst = max(worst, float(np.max(np.abs(wg[c] - wo[c]) * sc)) / den)
+    return worst
+
+
+def draw_sample(N, sample_size, seed=12345):
+    rng = np.random.default_rng(seed)
+    return np.sort(rng.choice(N, size=min(sample_size, N), replace=False))
+
+
+def sample_positions(off, sample):
+    return np.concatenate([np.arange(off[i], off[i + 1]) for i in sample])
+
+
+def cpu_oracle(X, sizes, P, ops, sample):
+    """The oracle, untuned: exact kNN (k-d tree + exact re-rank, against all nodes)
+    and weights (one LAPACK gesv per stencil) on a seeded sample, BLAS limited to
+    one thread.  Returns (baseline dict, sample offsets, idx, W)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import knn as oknn
+    from oracle import rbffd as orbf
+
+    N = X.shape[0]
+    Ps = np.broadcast_to(np.asarray(P), (N,))[sample]
+    with threadpool_limits(limits=1):
+        t = time.perf_counter()
+        c0 = time.process_time()
+        soff, sidx = oknn.knn_exact(X, sizes, nodes=sample)
+        Wo, sto = orbf.weights(X, soff, sidx, Ps, ops)
+        dt = time.perf_counter() - t
+        cpu_s = time.process_time() - c0
+    threads = max(1, int(round(cpu_s / dt)))   # threads the oracle kept busy on average
+    base = {"value": sample.size / dt, "unit": "stencils/s", "cores": threads, "kind": "oracle",
+            "sample": f"{sample.size} seeded random nodes of the same workload (kNN against all {N} nodes + weights), "
+                      f"{dt:.1f} s wall, {cpu_s:.1f} s CPU, BLAS limited to one thread"}
+    return base, soff, sidx, Wo
+
+
+def sample_errors(snap, sample, soff, sidx, Wo, ops, hn_sample):
+    """Scaled max error of each GPU form on the oracle sample, and stencil equality.
+    snap[form] = (weights at the sample positions [R, P], indices there or None)."""
+    err = {}
+    hn = np.repeat(hn_sample, np.diff(soff))
+    for f, (wg, ig) in snap.items():
+        if wg is not None:
+            err[f] = {"scaled_max_err": scaled_err(wg, Wo, ops, hn),
+                      "tolerance": 1e-10 if f == "f64" else 1e-9, "sample": int(sample.size)}
+        if ig is not None:
+            err["stencils_bit_exact_on_sample"] = bool(np.array_equal(ig, sidx))
+    return err
+
+
+def calib_copy(torch, dev):
+    src = torch.randn(1 << 27, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.neg(src, out=dst)
+    torch.cuda.synchronize()
+    print(f"[bench] calibration copy: 3 x (read {src.numel() * 8} B + write {dst.numel() * 8} B)",
+          file=sys.stderr, flush=True)
+
+
+def base_line(a, value, ms, dtype, config):
+    return {"metric": METRIC, "value": value, "unit": "stencils/s", "n_gpus": 1, "steps": a.steps,
+            "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def status_counts(st):
+    return {int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))}
+
+
+# ---------------------------------------------------------------- cube_sphere3d / large3d
+def bench_uniform(a, torch, rb, B, name):
+    import nodesets as ns
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    wl = ns.workload(name)
+    nd = wl["nodes"][0]
+    print(f"[bench] {name}: {nd.N} nodes generated in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+    n, P, ops = wl["n"], wl["P"], wl["ops"]
+    d = nd.d
+    m = math.comb(P + d, d)
+    R = len(ops)
+    N = nd.N
+    off = ns.offsets_from_sizes(np.full(N, n, dtype=np.int64))
+    nnz = int(off[-1])
+    X = torch.from_numpy(nd.X).to(dev)
+    offsets = torch.from_numpy(off).to(dev)
+    idx = torch.empty(nnz, dtype=torch.int32, device=dev)
+    ws = torch.empty(B.select_stencils_workspace(N, d, n), dtype=torch.uint8, device=dev)
+    w = torch.empty((R, nnz), dtype=torch.float64, device=dev)
+    status = torch.empty(N, dtype=torch.int8, device=dev)
+    row_ptr = torch.empty(N + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(nnz, dtype=torch.int32, device=dev)
+    vals = torch.empty((R, nnz), dtype=torch.float64, device=dev)
+    ctx = rb.context(dev)
+    timer = Timer(torch, ["select_stencils", "compute_weights", "assemble_csr"])
+    sample = draw_sample(N, a.cpu_sample)
+    pos_t = torch.from_numpy(sample_positions(off, sample)).to(dev)
+
+    def make_step(form):
+        def step(e):
+            if e:
+                e[0].record(timer.stream)
+            rb.select_stencils(X, offsets, n, idx=idx, workspace=ws, ctx=ctx)
+            if e:
+                e[1].record(timer.stream)
+            rb.compute_weights(X, offsets, idx, n, P, ops, precision=form, w=w, status=status, ctx=ctx)
+            if e:
+                e[2].record(timer.stream)
+            rb.assemble_csr(offsets, idx, w, n, row_ptr=row_ptr, col=col, vals=vals, ctx=ctx)
+            if e:
+                e[3].record(timer.stream)
+        return step
+
+    results, snap = {}, {}
+    forms = [a.form] if a.no_compare else [a.form] + [f for f in ("f64", "f32_ir") if f != a.form]
+    for f in forms:
+        ms, wall, ph = timer.run(make_step(f), a.steps, a.warmup)
+        st = status.cpu().numpy()
+        results[f] = dict(form=f, ms_per_step=ms, wall_ms_per_step=wall, phases_ms=ph,
+                          stencils_per_s=N / (ms / 1e3),
+                          knn_weights_stencils_per_s=N / ((ph["select_stencils"] + ph["compute_weights"]) / 1e3),
+                          status_counts=status_counts(st), fallback_fraction=float(np.mean(st == rb.ST_FALLBACK)))
+        if not a.no_cpu:
+            snap[f] = (w[:, pos_t].cpu().numpy(), idx[pos_t].cpu().numpy() if f == forms[0] else None)
+        print(f"[bench] {name} {f}: {ms:.3f} ms/step  phases {ph}", file=sys.stderr, flush=True)
+
+    main = results[a.form]
+    flop = weights_flops(n, m, d, R)
+    achieved = flop * N / (main["phases_ms"]["compute_weights"] / 1e3) / 1e12
+    M = n + m
+    if M > 64:
+        kernel = "k_weights_f64<128>"
+    elif a.form == "f32_ir":
+        kernel = "k_weights_ir<56> + k_weights_f64<56> (fallback pass)"
+    else:
+        kernel = "k_weights_f64<56>"
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_TFLOPS,
+                "traffic": recorded_traffic(a.form) if name == "cube_sphere3d" else None,
+                "kernel": kernel, "flop_per_stencil": flop, "stencils_per_launch": N}
+    phases_roofline = {}
+    for ph_name, per in (("select_stencils", knn_bytes(n, d)), ("assemble_csr", csr_bytes(n, R))):
+        gbs = per * N / (main["phases_ms"][ph_name] / 1e3) / 1e9
+        phases_roofline[ph_name] = {"bound": "hbm", "bytes_per_stencil": per, "achieved_GBs": gbs,
+                                    "frac": gbs / PEAK_HBM_GBS}
+    label = {"cube_sphere3d": "cube_minus_sphere_3d", "large3d": "cube_minus_64_balls_3d"}[name]
+    out = base_line(a, main["stencils_per_s"], main["ms_per_step"], "f32+f64" if a.form == "f32_ir" else "f64",
+                    {"workload": label, "N": N, "nnz": nnz, "n": n, "degree": P, "m": m, "ops": list(ops),
+                     "phs_power": 3, "form": a.form, "step": "select_stencils + compute_weights + assemble_csr"})
+    out.update(roofline=roofline, phases_roofline=phases_roofline, forms=results)
+    if "f64" in results and "f32_ir" in results:
+        out["mixed_vs_f64"] = (results["f32_ir"]["knn_weights_stencils_per_s"] /
+                               results["f64"]["knn_weights_stencils_per_s"])
+    if a.calib_copy:
+        calib_copy(torch, dev)
+    if not a.no_cpu:
+        base, soff, sidx, Wo = cpu_oracle(nd.X, n, P, ops, sample)
+        out["cpu_baseline"] = base
+        out["error"] = sample_errors(snap, sample, soff, sidx, Wo, ops, nd.h[sample])
+    return out
+
+
+# ---------------------------------------------------------------- mixed batch
+def bench_mixed(a, torch, rb, B):
+    import nodesets as ns
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    parts = ns.mixed_domains(a.per_domain)
+    print(f"[bench] mixed: nodes generated in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+    ctx = rb.context(dev)
+    doms, meta, flop_total, N_total = [], [], 0.0, 0
+    for nd, P, n in parts:
+        off = ns.offsets_from_sizes(n)
+        X = torch.from_numpy(nd.X).to(dev)
+        od = torch.from_numpy(off).to(dev)
+        nmax = int(n.max())
+        ws = torch.empty(B.select_stencils_workspace(nd.N, nd.d, nmax), dtype=torch.uint8, device=dev)
+        idx = torch.empty(int(off[-1]), dtype=torch.int32, device=dev)
+        rb.select_stencils(X, od, nmax, idx=idx, workspace=ws, ctx=ctx)
+        ops = ("lap", "dx", "dy") + (("dz",) if nd.d == 3 else ())
+        D = rb.Domain(X, od, idx, nmax, torch.from_numpy(P).to(dev), ops)
+        R = len(ops)
+        csr = (torch.empty(nd.N + 1, dtype=torch.int64, device=dev), torch.empty_like(idx),
+               torch.empty((R, idx.numel()), dtype=torch.float64, device=dev))
+        doms.append(D)
+        m = np.array([math.comb(int(p) + nd.d, nd.d) for p in P])
+        nn = n.astype(np.float64)
+        flop_total += float(np.sum((2.0 / 3.0) * (nn + m) ** 3 + 2.0 * R * (nn + m) ** 2 + (3 * nd.d + 1) * nn * nn))
+        N_total += nd.N
+        meta.append(dict(nd=nd, P=P, n=n, off=off, ws=ws, nmax=nmax, ops=ops, csr=csr))
+    wsb = torch.empty(B.batched_workspace(doms), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    plan = rb.autotune_batched(doms, precision=a.form, workspace=wsb)
+    tune_s = time.perf_counter() - t
+    print(f"[bench] mixed: plan {plan} tuned in {tune_s:.1f} s", file=sys.stderr, flush=True)
+    timer = Timer(torch, ["select_stencils", "compute_weights", "assemble_csr"])
+
+    def make_step(form):
+        def step(e):
+            if e:
+                e[0].record(timer.stream)
+            for D, mt in zip(doms, meta):
+                rb.select_stencils(D.X, D.offsets, mt["nmax"], idx=D.idx, workspace=mt["ws"], ctx=ctx)
+            if e:
+                e[1].record(timer.stream)
+            rb.compute_weights_batched(doms, precision=form, workspace=wsb, ctx=ctx)
+            if e:
+                e[2].record(timer.stream)
+            for D, mt in zip(doms, meta):
+                rp, cl, vl = mt["csr"]
+                rb.assemble_csr(D.offsets, D.idx, D.w, mt["nmax"], row_ptr=rp, col=cl, vals=vl, ctx=ctx)
+            if e:
+                e[3].record(timer.stream)
+        return step
+
+    per = max(1, a.cpu_sample // len(meta))
+    samples = [draw_sample(mt["nd"].N, per, seed=12345 + k) for k, mt in enumerate(meta)]
+    spos = [torch.from_numpy(sample_positions(mt["off"], smp)).to(dev) for mt, smp in zip(meta, samples)]
+    results, snap = {}, {}
+    forms = [a.form] if a.no_compare else [a.form] + [f for f in ("f64", "f32_ir") if f != a.form]
+    for f in forms:
+        ms, wall, ph = timer.run(make_step(f), a.steps, a.warmup)
+        sts = np.concatenate([D.status.cpu().numpy() for D in doms])
+        results[f] = dict(form=f, ms_per_step=ms, wall_ms_per_step=wall, phases_ms=ph,
+                          stencils_per_s=N_total / (ms / 1e3),
+                          knn_weights_stencils_per_s=N_total / ((ph["select_stencils"] + ph["compute_weights"]) / 1e3),
+                          status_counts=status_counts(sts), fallback_fraction=float(np.mean(sts == rb.ST_FALLBACK)))
+        if not a.no_cpu:
+            snap[f] = [D.w[:, p].cpu().numpy() for D, p in zip(doms, spos)]
+        print(f"[bench] mixed {f}: {ms:.3f} ms/step  phases {ph}", file=sys.stderr, flush=True)
+    main = results[a.form]
+    achieved = flop_total / (main["phases_ms"]["compute_weights"] / 1e3) / 1e12
+    nnz_total = int(sum(mt["off"][-1] for mt in meta))
+    out = base_line(a, main["stencils_per_s"], main["ms_per_step"], "f32+f64" if a.form == "f32_ir" else "f64",
+                    {"workload": "mixed_2d3d_4_domains", "N": N_total, "nnz": nnz_total,
+                     "domains": [dict(name=mt["nd"].meta["domain"], N=mt["nd"].N, d=mt["nd"].d) for mt in meta],
+                     "n": "U[max(12, ceil(1.5 m)), 70] per node", "degree": "U{2,3,4} per node", "phs_power": 3,
+                     "form": a.form, "plan": plan, "autotune_s": tune_s,
+                     "step": "select_stencils x4 + compute_weights_batched + assemble_csr x4"})
+    out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                       "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
+                       "kernel": "k_bpersist (refined pass + FP64 fallback pass)" if a.form == "f32_ir"
+                       else "k_bpersist", "flop_per_stencil": flop_total / N_total, "stencils_per_launch": N_total}
+    out["forms"] = results
+    if "f64" in results and "f32_ir" in results:
+        out["mixed_vs_f64"] = (results["f32_ir"]["knn_weights_stencils_per_s"] /
+                               results["f64"]["knn_weights_stencils_per_s"])
+    if not a.no_cpu:
+        tot_n, tot_t, err, cores = 0, 0.0, {}, 1
+        for k, mt in enumerate(meta):
+            sample = samples[k]
+            base, soff, sidx, Wo = cpu_oracle(mt["nd"].X, mt["n"], mt["P"].astype(np.int64), mt["ops"], sample)
+            tot_n += sample.size
+            tot_t += sample.size / base["value"]
+            cores = max(cores, base["cores"])
+            s = {f: (snap[f][k], None) for f in snap}
+            e = sample_errors(s, sample, soff, sidx, Wo, mt["ops"], mt["nd"].h[sample])
+            for f, v in e.items():
+                err.setdefault(f, []).append(v["scaled_max_err"])
+        out["cpu_baseline"] = {"value": tot_n / tot_t, "unit": "stencils/s", "cores": cores, "kind": "oracle",
+                               "sample": f"{tot_n} seeded random nodes over the 4 domains "
+                                         f"(kNN against all nodes + weights), BLAS limited to one thread"}
+        out["error"] = {f: {"scaled_max_err": max(v), "tolerance": 1e-10 if f == "f64" else 1e-9}
+                        for f, v in err.items()}
+    return out
+
+
+# ---------------------------------------------------------------- learned surrogate
+def bench_learned(a, torch, rb, B):
+    import nodesets as ns
+    from paper_1912_13282_amd import surrogate as S
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    data = S.build_training_set(S.training_node_sets(a.train_sets), device=dev)
+    torch.cuda.synchronize()
+    prep_s = time.perf_counter() - t
+    S_n = data.feat.shape[0]
+    st = S.TrainState.init(22, device=dev)
+    batch = 8192
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    hist = S.train(st, data, epochs=a.train_epochs, batch=batch, lr=2e-3, seed=4)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t
+    print(f"[bench] learned: {S_n} training stencils prepared in {prep_s:.1f} s; {st.step} Adam steps "
+          f"in {train_s:.1f} s, loss {hist[0]:.3e} -> {hist[-1]:.3e}", file=sys.stderr, flush=True)
+    del data
+
+    # quality on the 2,007-node disk (seed 1001)
+    from oracle import poisson as opoi
+    q = ns.disk(ns.DISK_H, 1001)
+    Xq = torch.from_numpy(q.X).to(dev)
+    oq = torch.arange(0, (q.N + 1) * 15, 15, dtype=torch.int64, device=dev)
+    iq = rb.select_stencils(Xq, oq, 15)
+    wpq, _ = rb.compute_weights(Xq, oq, iq, 15, 2, ("lap",), precision="f64")
+    wtq, stq = S.surrogate_laplacian(Xq, oq, iq, st.params)
+    wzq, _ = S.surrogate_laplacian(Xq, oq, iq, torch.zeros_like(st.params))
+    iqn = iq.cpu().numpy()
+    quality = {}
+    for nm, wv in (("plain", wpq[0]), ("trained", wtq), ("zero_network", wzq)):
+        wn = wv.cpu().numpy()
+        approx = (wn * opoi.u0(q.X)[iqn]).reshape(-1, 15).sum(1)
+        quality[nm] = {"poisson_max_err": opoi.solve_dirichlet(q.X, q.is_boundary, oq.cpu().numpy(), iqn, wn)[1],
+                       "e_h": float(np.abs(approx - opoi.lap_u0(q.X))[~q.is_boundary].max())}
+    quality["accepted_fraction"] = float((stq.cpu().numpy() == rb.ST_SURROGATE).mean())
+
+    # throughput on a 1.7M-node disk
+    nd = ns.disk(ns.DISK_H / 30.0, 1001)
+    N = nd.N
+    X = torch.from_numpy(nd.X).to(dev)
+    off = torch.arange(0, (N + 1) * 15, 15, dtype=torch.int64, device=dev)
+    idx = torch.empty(N * 15, dtype=torch.int32, device=dev)
+    ws = torch.empty(B.select_stencils_workspace(N, 2, 15), dtype=torch.uint8, device=dev)
+    w = torch.empty((1, N * 15), dtype=torch.float64, device=dev)
+    status = torch.empty(N, dtype=torch.int8, device=dev)
+    ctx = rb.context(dev)
+    B.surrogate_load(st.params, ctx=ctx)
+    timer = Timer(torch, ["select_stencils", "compute_weights"])
+
+    def make_step(form):
+        def step(e):
+            if e:
+                e[0].record(timer.stream)
+            rb.select_stencils(X, off, 15, idx=idx, workspace=ws, ctx=ctx)
+            if e:
+                e[1].record(timer.stream)
+            if form == "surrogate":
+                B.surrogate_weights(X, off, idx, 15, w=w[0], status=status, ctx=ctx)
+            else:
+                rb.compute_weights(X, off, idx, 15, 2, ("lap",), precision=form, w=w, status=status, ctx=ctx)
+            if e:
+                e[2].record(timer.stream)
+        return step
+
+    results = {}
+    forms = ["surrogate"] if a.no_compare else ["surrogate", "f64", "f32_ir"]
+    wsnap = {}
+    for f in forms:
+        ms, wall, ph = timer.run(make_step(f), a.steps, a.warmup)
+        stn = status.cpu().numpy()
+        results[f] = dict(form=f, ms_per_step=ms, wall_ms_per_step=wall, phases_ms=ph,
+                          stencils_per_s=N / (ms / 1e3), status_counts=status_counts(stn))
+        wsnap[f] = w[0].cpu().numpy()
+        print(f"[bench] learned {f}: {ms:.3f} ms/step  phases {ph}", file=sys.stderr, flush=True)
+    main = results["surrogate"]
+    if "f64" in wsnap:
+        dv = (np.abs(wsnap["surrogate"] - wsnap["f64"]).reshape(-1, 15).max(1) /
+              np.abs(wsnap["f64"]).reshape(-1, 15).max(1))
+        quality["deviation_from_plain"] = {"median": float(np.median(dv)), "p99": float(np.quantile(dv, 0.99)),
+                                           "max": float(dv.max())}
+    t_w = main["phases_ms"]["compute_weights"] / 1e3
+    achieved = SURROGATE_FLOPS * N / t_w / 1e12
+    out = base_line(a, main["stencils_per_s"], main["ms_per_step"], "bf16+f32+f64",
+                    {"workload": "learned_laplacian_disk_2d", "N": N, "n": 15, "degree": 2, "m": 6, "ops": ["lap"],
+                     "network": "30-128-128-128-15 GELU", "training_stencils": S_n, "train_epochs": a.train_epochs,
+                     "batch": batch, "adam_steps": st.step, "train_s": train_s,
+                     "train_samples_per_s": st.step * batch / train_s, "loss_first_last": [hist[0], hist[-1]],
+                     "step": "select_stencils + surrogate_weights (projection + plain-solve fallback)"})
+    out["roofline"] = {"bound": "mfma", "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                       "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None,
+                       "kernel": "k_surrogate + k_weights_f64<24> (fallback pass)",
+                       "flop_per_stencil": SURROGATE_FLOPS, "stencils_per_launch": N,
+                       "hbm_GBs_algorithmic": SURROGATE_BYTES * N / t_w / 1e9}
+    out["forms"] = results
+    out["quality"] = quality
+    if "f64" in results:
+        out["learned_vs_f64"] = main["stencils_per_s"] / results["f64"]["stencils_per_s"]
+    if not a.no_cpu:
+        base, soff, sidx, Wo = cpu_oracle(nd.X, 15, 2, ("lap",), draw_sample(N, a.cpu_sample))
+        out["cpu_baseline"] = base
+    return out
+
+
 def main():
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -111,172 +538,17 @@ def main():
         sys.exit(2)
 
     import torch
-    import nodesets as ns
     import paper_1912_13282_amd as rb
-
-    dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    wl = ns.workload("cube_sphere3d")
-    nd = wl["nodes"][0]
-    n, P, ops = wl["n"], wl["P"], wl["ops"]
-    d = nd.d
-    m = math.comb(P + d, d)
-    R = len(ops)
-    N = nd.N
-    off = ns.offsets_from_sizes(np.full(N, n, dtype=np.int64))
-    nnz = int(off[-1])
-
-    X = torch.from_numpy(nd.X).to(dev)
-    offsets = torch.from_numpy(off).to(dev)
-    idx = torch.empty(nnz, dtype=torch.int32, device=dev)
     from paper_1912_13282_amd import _binding as B
-    ws = torch.empty(B.select_stencils_workspace(N, d, n), dtype=torch.uint8, device=dev)
-    w = torch.empty((R, nnz), dtype=torch.float64, device=dev)
-    status = torch.empty(N, dtype=torch.int8, device=dev)
-    row_ptr = torch.empty(N + 1, dtype=torch.int64, device=dev)
-    col = torch.empty(nnz, dtype=torch.int32, device=dev)
-    vals = torch.empty((R, nnz), dtype=torch.float64, device=dev)
-    ctx = rb.context(dev)
-    stream = torch.cuda.current_stream(dev)
 
-    def step(form, evs=None):
-        if evs:
-            evs[0].record(stream)
-        rb.select_stencils(X, offsets, n, idx=idx, workspace=ws, ctx=ctx)
-        if evs:
-            evs[1].record(stream)
-        rb.compute_weights(X, offsets, idx, n, P, ops, precision=form, w=w, status=status, ctx=ctx)
-        if evs:
-            evs[2].record(stream)
-        rb.assemble_csr(offsets, idx, w, n, row_ptr=row_ptr, col=col, vals=vals, ctx=ctx)
-        if evs:
-            evs[3].record(stream)
-
-    def run_form(form, K, W):
-        for _ in range(W):
-            step(form)
-        torch.cuda.synchronize()
-        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        wall = time.perf_counter()
-        t0.record(stream)
-        for k in range(K):
-            step(form, evs[k])
-        t1.record(stream)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - wall
-        total_ms = t0.elapsed_time(t1)
-        ph = np.array([[e[0].elapsed_time(e[1]), e[1].elapsed_time(e[2]), e[2].elapsed_time(e[3])] for e in evs])
-        st = status.cpu().numpy()
-        knn_ms, w_ms, csr_ms = ph.mean(axis=0)
-        return dict(form=form, ms_per_step=total_ms / K, wall_ms_per_step=1000.0 * wall / K,
-                    phases_ms=dict(select_stencils=knn_ms, compute_weights=w_ms, assemble_csr=csr_ms),
-                    stencils_per_s=N / ((total_ms / K) / 1000.0),
-                    knn_weights_stencils_per_s=N / ((knn_ms + w_ms) / 1000.0),
-                    status_counts={int(k): int(v) for k, v in zip(*np.unique(st, return_counts=True))},
-                    fallback_fraction=float(np.mean(st == rb.ST_FALLBACK)))
-
-    results = {}
-    forms = [a.form] if a.no_compare else [a.form] + [f for f in ("f64", "f32_ir") if f != a.form]
-    weights_snapshot = {}
-    for f in forms:
-        results[f] = run_form(f, a.steps, a.warmup)
-        weights_snapshot[f] = (w.cpu().numpy() if not a.no_cpu else None, idx.cpu().numpy() if f == forms[0] else None)
-        print(f"[bench] {f}: {results[f]['ms_per_step']:.3f} ms/step  phases {results[f]['phases_ms']}",
-              file=sys.stderr, flush=True)
-
-    main_r = results[a.form]
-    flop = weights_flops_per_stencil(n, m, d, R)
-    t_w = main_r["phases_ms"]["compute_weights"] / 1000.0
-    achieved = flop * N / t_w / 1e12
-    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_TFLOPS, "traffic": recorded_traffic(a.form),
-                "kernel": "k_weights_ir + k_weights_f64(fallback pass)" if a.form == "f32_ir" else "k_weights_f64",
-                "flop_per_stencil": flop, "stencils_per_launch": N}
-    phases_roofline = {
-        "select_stencils": {"bound": "hbm", "bytes_per_stencil": knn_bytes_per_stencil(n, d),
-                            "achieved_GBs": knn_bytes_per_stencil(n, d) * N / (main_r["phases_ms"]["select_stencils"] / 1e3) / 1e9},
-        "assemble_csr": {"bound": "hbm", "bytes_per_stencil": csr_bytes_per_stencil(n, R),
-                         "achieved_GBs": csr_bytes_per_stencil(n, R) * N / (main_r["phases_ms"]["assemble_csr"] / 1e3) / 1e9},
-    }
-    for k in phases_roofline:
-        phases_roofline[k]["frac"] = phases_roofline[k]["achieved_GBs"] / PEAK_HBM_GBS
-
-    out = {
-        "metric": METRIC, "value": main_r["stencils_per_s"], "unit": "stencils/s", "n_gpus": 1,
-        "steps": a.steps, "warmup": a.warmup, "ms_per_step": main_r["ms_per_step"], "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64" if a.form == "f32_ir" else "f64", "data": "synthetic",
-        "config": {"workload": "cube_minus_sphere_3d", "N": N, "nnz": nnz, "n": n, "degree": P, "m": m,
-                   "ops": list(ops), "phs_power": 3, "form": a.form,
-                   "step": "select_stencils + compute_weights + assemble_csr"},
-        "roofline": roofline,
-        "phases_roofline": phases_roofline,
-        "forms": results,
-    }
-    if "f64" in results and "f32_ir" in results:
-        out["mixed_vs_f64"] = results["f32_ir"]["knn_weights_stencils_per_s"] / results["f64"]["knn_weights_stencils_per_s"]
-
-    if a.calib_copy:
-        src = torch.randn(1 << 27, dtype=torch.float64, device=dev)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            torch.neg(src, out=dst)
-        torch.cuda.synchronize()
-        print(f"[bench] calibration copy: 3 x (read {src.numel() * 8} B + write {dst.numel() * 8} B)",
-              file=sys.stderr, flush=True)
-        del src, dst
-
-    if not a.no_cpu:
-        out["cpu_baseline"], out["error"] = cpu_baseline(nd, off, n, P, ops, weights_snapshot, a.cpu_sample)
+    torch.cuda.set_device(torch.device("cuda:0"))
+    if a.workload in ("cube_sphere3d", "large3d"):
+        out = bench_uniform(a, torch, rb, B, a.workload)
+    elif a.workload == "mixed":
+        out = bench_mixed(a, torch, rb, B)
+    else:
+        out = bench_learned(a, torch, rb, B)
     print(json.dumps(out), flush=True)
-
-
-def cpu_baseline(nd, off, n, P, ops, snap, sample_size):
-    """The oracle, untuned, on one host core: exact kNN (k-d tree + exact re-rank)
-    and weights (one LAPACK gesv per stencil) for a seeded sample of nodes.  The
-    same sample also measures the GPU forms' error against the oracle."""
-    from threadpoolctl import threadpool_limits
-
-    from oracle import knn as oknn
-    from oracle import rbffd as orbf
-
-    rng = np.random.default_rng(12345)
-    sample = np.sort(rng.choice(nd.N, size=min(sample_size, nd.N), replace=False))
-    with threadpool_limits(limits=1):
-        t = time.perf_counter()
-        c0 = time.process_time()
-        soff, sidx = oknn.knn_exact(nd.X, n, nodes=sample)
-        Wo, _ = orbf.weights(nd.X, soff, sidx, P, ops)
-        dt = time.perf_counter() - t
-        cpu_s = time.process_time() - c0
-    st_idx = sidx.reshape(sample.size, n)
-    threads = max(1, int(round(cpu_s / dt)))   # threads the oracle kept busy on average
-    cpu = {"value": sample.size / dt, "unit": "stencils/s", "cores": threads, "kind": "oracle",
-           "sample": f"{sample.size} seeded random nodes of the same workload (kNN against all {nd.N} nodes + weights), "
-                     f"{dt:.1f} s wall, {cpu_s:.1f} s CPU, BLAS limited to one thread"}
-    # error of each GPU form on the sample (C9-style scaled max-norm)
-    err = {}
-    h = nd.h[0]
-    for f, (wg, ig) in snap.items():
-        if wg is None:
-            continue
-        pos = (off[sample][:, None] + np.arange(n)[None, :]).reshape(-1)
-        worst = 0.0
-        for c, op in enumerate(ops):
-            sc = h ** (2 if op == "lap" else 1)
-            den = max(1.0, float(np.max(np.abs(Wo[c]) * sc)))
-            worst = max(worst, float(np.max(np.abs(wg[c, pos] - Wo[c]) * sc)) / den)
-        err[f] = {"scaled_max_err": worst, "tolerance": 1e-10 if f == "f64" else 1e-9, "sample": int(sample.size)}
-    stencils_match = None
-    for f, (wg, ig) in snap.items():
-        if ig is not None:
-            pos = (off[sample][:, None] + np.arange(n)[None, :])
-            stencils_match = bool(np.array_equal(ig[pos], st_idx))
-    err["stencils_bit_exact_on_sample"] = stencils_match
-    return cpu, err
 
 
 if __name__ == "__main__":

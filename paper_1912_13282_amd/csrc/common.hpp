@@ -120,6 +120,21 @@ __device__ __forceinline__ float wave_max_dpp_f(float v) {
     v = fmaxf(v, dpp_f<0x143, 0xC>(v));
     return readlane_f(v, 63);
 }
+// Wave-wide maximum of an int through DPP; INT_MIN fills the lanes a stage does
+// not reach, so every stage folds into one v_max_i32 with a DPP operand.  Lane 63
+// ends with the total, returned uniformly.  (Non-negative floats compare like
+// their bit patterns, which makes this the pivot search on magnitudes.)
+__device__ __forceinline__ int wave_max_dpp_i(int v) {
+    constexpr int LO = -2147483647 - 1;
+    v = max(v, __builtin_amdgcn_update_dpp(LO, v, 0xB1, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(LO, v, 0x4E, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(LO, v, 0x141, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(LO, v, 0x140, 0xF, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(LO, v, 0x142, 0xA, 0xF, false));
+    v = max(v, __builtin_amdgcn_update_dpp(LO, v, 0x143, 0xC, 0xF, false));
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
 // Wave-wide sum through DPP in a fixed order (deterministic); uniform result.
 __device__ __forceinline__ double wave_sum_dpp_d(double v) {
     v += dpp_d<0xB1, 0xF>(v);
@@ -138,6 +153,9 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
+
+// lanes where pred holds (wave64), without materialising pred in a register
+__device__ __forceinline__ uint64_t ballot64(bool pred) { return __builtin_amdgcn_ballot_w64(pred); }
 
 // first set lane of a wave-uniform 64-bit mask (mask != 0)
 __device__ __forceinline__ int first_lane(uint64_t m) { return __builtin_ctzll(m); }

@@ -167,7 +167,7 @@ __device__ __forceinline__ bool load_frame_g(const StencilArgs& a, int64_t off, 
 #pragma unroll
     for (int t = 0; t < RPL; ++t)
         for (int q = 0; q < 3; ++q) F.xh[t][q] = o[t][q] * F.inv_s;
-    return __ballot(bad) == 0;
+    return ballot64(bad) == 0;
 }
 
 // LDS layout (in doubles) of the one-row-per-lane solvers, sized for any m.
@@ -336,16 +336,18 @@ __device__ __forceinline__ bool gauss_jordan(T (&row)[MAXM], T (&rhs)[NR], T* pr
     bool piv = lane >= MAXM;
     int mystep = -1;
     T invd = (T)0;
-    bool bad = false;
+    int pmin = 0x7F7FFFFF, pmax = 0;  // bit patterns of the smallest / largest pivot magnitude
 #pragma unroll
     for (int k = 0; k < MAXM; ++k) {
         if (GUARD && k >= M) continue;
         // pivot search on float magnitudes (partial pivoting needs a large pivot,
-        // not the exact maximum); the first lane with the maximum wins
-        const float cand = piv ? -1.0f : (float)fabs(row[k]);
-        const float mx = wave_max_dpp_f(cand);
-        bad = bad || !(mx > 0.0f) || !__builtin_isfinite(mx);
-        const uint64_t b = __ballot(!piv && cand == mx);
+        // not the exact maximum), compared as bit patterns (a NaN wins and marks
+        // the system bad); the first lane with the maximum wins
+        const int cand = piv ? -1 : __float_as_int((float)fabs(row[k]));
+        const int mi = wave_max_dpp_i(cand);
+        pmin = min(pmin, mi);  // a zero pivot: singular
+        pmax = max(pmax, mi);  // an infinite or NaN pivot
+        const uint64_t b = ballot64(!piv && cand == mi);
         const int p = first_lane(b);
         T* buf = prow + (k & 1) * PRW;
         const bool me = (lane == p);
@@ -396,7 +398,7 @@ __device__ __forceinline__ bool gauss_jordan(T (&row)[MAXM], T (&rhs)[NR], T* pr
 #pragma unroll
         for (int q = 0; q < NR; ++q) sol[q] = sol_lds[lane * NR + q];
     wave_lds_sync();
-    return __ballot(bad) == 0;
+    return pmin > 0 && pmax < 0x7F800000;  // wave-uniform
 }
 
 // Replay of the recorded float32 elimination on right-hand sides b (one per
@@ -407,7 +409,7 @@ __device__ __forceinline__ void gj_replay(const float (&row)[MAXM], float (&b)[N
 #pragma unroll
     for (int k = 0; k < MAXM; ++k) {
         if (GUARD && k >= M) continue;
-        const int p = first_lane(__ballot(mystep == k));
+        const int p = first_lane(ballot64(mystep == k));
         const float l = (lane == p) ? 0.0f : row[k];
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
@@ -689,11 +691,11 @@ __device__ __forceinline__ void stencil_f64_big(const StencilArgs& a, int64_t no
             break;
         }
         int p, ps = 0;
-        const uint64_t b0 = __ballot(!piv[0] && fabs(row[0][k]) == mx);
+        const uint64_t b0 = ballot64(!piv[0] && fabs(row[0][k]) == mx);
         if (b0) {
             p = first_lane(b0);
         } else {
-            p = first_lane(__ballot(!piv[1] && fabs(row[1][k]) == mx));
+            p = first_lane(ballot64(!piv[1] && fabs(row[1][k]) == mx));
             ps = 1;
         }
         const double pv = readlane_d(ps == 0 ? row[0][k] : row[1][k], p);
@@ -729,11 +731,11 @@ __device__ __forceinline__ void stencil_f64_big(const StencilArgs& a, int64_t no
     if (ok) {
         for (int k = M - 1; k >= 0; --k) {
             int p, ps = 0;
-            const uint64_t b0 = __ballot(step[0] == k);
+            const uint64_t b0 = ballot64(step[0] == k);
             if (b0) {
                 p = first_lane(b0);
             } else {
-                p = first_lane(__ballot(step[1] == k));
+                p = first_lane(ballot64(step[1] == k));
                 ps = 1;
             }
 #pragma unroll
