@@ -112,6 +112,7 @@ def parse():
     ap.add_argument("--no-compare", action="store_true", help="time only the reported form")
     ap.add_argument("--cpu-sample", type=int, default=30000)
     ap.add_argument("--per-domain", type=int, default=2_000_000, help="mixed: nodes per domain")
+    ap.add_argument("--tune-per-domain", type=int, default=200_000, help="mixed: nodes per domain of the tuning batch")
     ap.add_argument("--train-sets", type=int, default=5000, help="learned: training node sets (2,008 nodes each)")
     ap.add_argument("--train-epochs", type=int, default=8)
     ap.add_argument("--calib-copy", action="store_true",
@@ -345,10 +346,22 @@ def bench_mixed(a, torch, rb, B):
         N_total += nd.N
         meta.append(dict(nd=nd, P=P, n=n, off=off, ws=ws, nmax=nmax, ops=ops, csr=csr))
     wsb = torch.empty(B.batched_workspace(doms), dtype=torch.uint8, device=dev)
+    # the plan is tuned on a smaller batch of the same recipe (every candidate
+    # plan runs the whole tuning batch), then used for the full batch
+    tdoms = []
+    for nd, P, n in ns.mixed_domains(a.tune_per_domain):
+        off = ns.offsets_from_sizes(n)
+        X = torch.from_numpy(nd.X).to(dev)
+        od = torch.from_numpy(off).to(dev)
+        idx = rb.select_stencils(X, od, int(n.max()), ctx=ctx)
+        ops = ("lap", "dx", "dy") + (("dz",) if nd.d == 3 else ())
+        tdoms.append(rb.Domain(X, od, idx, int(n.max()), torch.from_numpy(P).to(dev), ops))
     torch.cuda.synchronize()
+    print(f"[bench] mixed: tuning on {sum(D.X.shape[0] for D in tdoms)} stencils", file=sys.stderr, flush=True)
     t = time.perf_counter()
-    plan = rb.autotune_batched(doms, precision=a.form, workspace=wsb)
+    plan = rb.autotune_batched(tdoms, precision=a.form, ctx=ctx)
     tune_s = time.perf_counter() - t
+    del tdoms
     print(f"[bench] mixed: plan {plan} tuned in {tune_s:.1f} s", file=sys.stderr, flush=True)
     timer = Timer(torch, ["select_stencils", "compute_weights", "assemble_csr"])
 
@@ -392,7 +405,7 @@ def bench_mixed(a, torch, rb, B):
                     {"workload": "mixed_2d3d_4_domains", "N": N_total, "nnz": nnz_total,
                      "domains": [dict(name=mt["nd"].meta["domain"], N=mt["nd"].N, d=mt["nd"].d) for mt in meta],
                      "n": "U[max(12, ceil(1.5 m)), 70] per node", "degree": "U{2,3,4} per node", "phs_power": 3,
-                     "form": a.form, "plan": plan, "autotune_s": tune_s,
+                     "form": a.form, "plan": plan, "autotune_s": tune_s, "tune_per_domain": a.tune_per_domain,
                      "step": "select_stencils x4 + compute_weights_batched + assemble_csr x4"})
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                        "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,

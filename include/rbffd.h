@@ -149,11 +149,14 @@ rbf_status rbf_assemble_csr(rbf_ctx* ctx, int64_t N, const int64_t* offsets,
 
 /* ------------------------------------------------------------------------ *
  * Batched persistent form: the weights of several node sets at once, mixing
- * dimension (2D/3D), augmentation degree (2..4, per node) and stencil size,
- * in one persistent launch per precision (the FP32+refine form adds a second
- * launch for its FP64 fallbacks).  Each domain is described as for
- * rbf_compute_weights; every stencil's system size n_i + m must be <= 128.
- * Results, status codes and layouts are those of rbf_compute_weights.
+ * dimension (2D/3D), augmentation degree (0..4, per node) and stencil size.
+ * The stencils of all domains are sorted into size classes (n_i + m <= 24,
+ * 32, 48, 64, 128); each class runs one persistent launch over all domains
+ * (the FP32+refine form adds one FP64 launch per class for its fallbacks;
+ * systems above 64 unknowns are solved in FP64 and reported FALLBACK).  Each
+ * domain is described as for rbf_compute_weights; a stencil with n_i + m > 128
+ * gets BADSIZE.  Results, status codes and layouts are those of
+ * rbf_compute_weights.
  * Workspace: rbf_batched_workspace.  The plan (chunk of stencils per grab,
  * waves per compute unit) is the context's, set by rbf_autotune_batched or
  * rbf_set_plan (default chunk 4, 8 waves per CU).  At most 16 domains.

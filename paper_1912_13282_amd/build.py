@@ -29,6 +29,9 @@ FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
     # packed FP32 VALU forms are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # the 128-step eliminations must unroll completely (register arrays are
+    # indexed by the step), which is above LLVM's default size limit
+    "-mllvm", "-pragma-unroll-threshold=1000000",
     "-I", os.path.join(ROOT, "include"),
 ]
 

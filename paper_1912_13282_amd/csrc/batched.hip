@@ -1,55 +1,37 @@
 // Batched persistent RBF-FD weights: stencils of several node sets, mixed
-// dimension (2D/3D), augmentation degree (2..4) and size, in ONE persistent
-// launch per precision.
+// dimension (2D/3D), augmentation degree (2..4) and size, in one persistent
+// launch per size class and precision.
 //
-//   k_bclassify : class of every stencil = (d, degree, size bucket); counts
-//   k_bscan     : class offsets (one block)
+//   k_bclassify : size class of every stencil (smallest MAXM >= n + m) and its
+//                 rank inside the class
+//   k_bscan     : class offsets (one block); resets the work counters
 //   k_bscatter  : class-sorted work list of (domain, node) items
-//   k_bpersist  : a fixed grid of single-wave workgroups; each wave grabs
-//                 `chunk` items at a time from an atomic counter (so uneven
-//                 stencils balance dynamically) and runs the class's solver:
-//                 size bucket <= 64 -> one row per lane Gauss-Jordan with the
-//                 runtime system size guarded; <= 128 -> two rows per lane LU.
-// The work list is sorted by class, so waves running at the same time mostly
-// execute the same code.  The plan (chunk, waves per CU) comes from
-// rbf_autotune_batched, which times candidate plans on the caller's batch.
-#include "weights_kernels.hpp"
+//   k_bclass    : per class, a fixed grid of single-wave workgroups pulling
+//                 chunks of the class's range from an atomic counter
+//                 (batched_kernels.hpp, instantiated in bcls_*.hip)
+//   k_breject   : NaN weights and BADSIZE for invalid stencils
+// The FP32+refinement form adds one FP64 pass per class over its fallbacks.
+// The plan (chunk, waves per CU) comes from rbf_autotune_batched, which times
+// candidate plans on the caller's batch.
+#include "batched_kernels.hpp"
 
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
-#include <chrono>
 #include <string>
-#include <vector>
 
 namespace rbf {
 
-constexpr int BMAX_DOMS = 16;
-constexpr int SMALL = 64;
-constexpr int BIG = 128;
-constexpr int NCLS = 2 * 3 * 2;  // d in {2,3} x degree in {2,3,4} x bucket in {<=64, <=112}
-constexpr int REJECT = NCLS;     // invalid stencils (bad size / degree / index)
+static BLaunchFn g_bclass[NBCLS];
 
-__host__ __device__ constexpr int cls_id(int d, int P, int big) { return ((d - 2) * 3 + (P - 2)) * 2 + big; }
+void register_bclass(int maxm, BLaunchFn fn) {
+    for (int c = 0; c < NBCLS; ++c)
+        if (bcls_maxm(c) == maxm) g_bclass[c] = fn;
+}
 
-struct BDom {
-    StencilArgs a;         // a.d is the domain's dimension, a.P its uniform degree
-    const int8_t* degree;  // per-node degree, or NULL
-    int64_t first;         // first global item of this domain
-};
-
-struct BParams {
-    int n_doms;
-    int64_t total;
-    BDom dom[BMAX_DOMS];
-};
-
-__device__ __forceinline__ int find_dom(const BParams& bp, int64_t g) {
-    int d = 0;
-    for (int k = 1; k < bp.n_doms; ++k)
-        if (g >= bp.dom[k].first) d = k;
-    return d;
+__global__ __launch_bounds__(64) void k_bzero(int* __restrict__ counts) {
+    if (threadIdx.x <= BREJECT) counts[threadIdx.x] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_bclassify(const BParams* __restrict__ bpp, int* __restrict__ counts,
@@ -57,15 +39,16 @@ __global__ __launch_bounds__(256) void k_bclassify(const BParams* __restrict__ b
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const BParams& bp = *bpp;
     if (g >= bp.total) return;
-    const int di = find_dom(bp, g);
-    const BDom& D = bp.dom[di];
+    const BDom& D = bp.dom[find_dom(bp, g)];
     const int64_t i = g - D.first;
     const int P = D.degree ? (int)D.degree[i] : D.a.P;
-    const int64_t n = D.a.offsets[i + 1] - D.a.offsets[i];
-    int c = REJECT;
-    if (P >= 2 && P <= 4 && n >= 1 && n <= D.a.n_max) {
+    const int64_t off = D.a.offsets[i];
+    const int64_t n = D.a.offsets[i + 1] - off;
+    int c = BREJECT;
+    if (P >= 0 && P <= 4 && n >= 1 && n <= D.a.n_max && off >= 0 && off + n <= D.a.nnz) {
         const int M = (int)n + binom(P + D.a.d, D.a.d);
-        if (M <= BIG) c = cls_id(D.a.d, P, M > SMALL ? 1 : 0);
+        for (int k = NBCLS - 1; k >= 0; --k)
+            if (M <= bcls_maxm(k)) c = k;
     }
     const int r = atomicAdd(&counts[c], 1);
     cls_rank[2 * g] = (uint32_t)c;
@@ -73,17 +56,16 @@ __global__ __launch_bounds__(256) void k_bclassify(const BParams* __restrict__ b
 }
 
 __global__ __launch_bounds__(64) void k_bscan(const int* __restrict__ counts, int64_t* __restrict__ starts,
-                                              unsigned long long* __restrict__ counter) {
+                                              unsigned long long* __restrict__ counters) {
     if (threadIdx.x == 0) {
         int64_t s = 0;
-        for (int c = 0; c <= NCLS; ++c) {
+        for (int c = 0; c <= BREJECT; ++c) {
             starts[c] = s;
             s += counts[c];
         }
-        starts[NCLS + 1] = s;
-        counter[0] = 0;
-        counter[1] = 0;
+        starts[BREJECT + 1] = s;
     }
+    if (threadIdx.x < NCOUNTERS) counters[threadIdx.x] = 0;
 }
 
 __global__ __launch_bounds__(256) void k_bscatter(const BParams* __restrict__ bpp, const uint32_t* __restrict__ cls_rank,
@@ -94,66 +76,19 @@ __global__ __launch_bounds__(256) void k_bscatter(const BParams* __restrict__ bp
     items[starts[c] + r] = (uint64_t)g;
 }
 
-// LDS (in doubles) of the largest solver in the batch
-constexpr int BLDS = RowLds<SMALL>::TOTAL > big_lds_doubles<BIG>() ? RowLds<SMALL>::TOTAL : big_lds_doubles<BIG>();
-
-// class c -> solver: one row per lane (guarded Gauss-Jordan) for the <= 64
-// bucket, two rows per lane float64 LU for the <= 128 bucket
-template <int PREC>
-__device__ __forceinline__ void run_class(int c, const StencilArgs& a, int64_t node, int P, double* lds,
-                                          int max_refine, double refine_tol) {
-    if (c >= NCLS) {
-        const int64_t off = a.offsets[node];
-        const int64_t n = a.offsets[node + 1] - off;
-        reject_stencil(a, node, off, (n < 0 || off < 0 || off + n > a.nnz) ? 0 : n, RBF_ST_BADSIZE);
-    } else if (c & 1) {
-        stencil_f64_big<BIG>(a, node, P, lds);
-    } else if constexpr (PREC == RBF_PREC_F64) {
-        stencil_f64_rows<SMALL, true>(a, node, P, lds);
-    } else {
-        stencil_ir_rows<SMALL, true>(a, node, P, lds, max_refine, refine_tol);
-    }
-}
-
-// fallback_pass: solve (float64) only the items whose status is FALLBACK
-template <int PREC>
-__global__ __launch_bounds__(64) void k_bpersist(const BParams* __restrict__ bpp, const uint64_t* __restrict__ items,
-                                                 const int64_t* __restrict__ starts,
-                                                 unsigned long long* __restrict__ counter, int chunk, int max_refine,
-                                                 double refine_tol, int fallback_pass) {
-    __shared__ __attribute__((aligned(16))) double lds[BLDS];
+// invalid stencils: one wave per item, NaN weights inside the valid part of the arrays
+__global__ __launch_bounds__(256) void k_breject(const BParams* __restrict__ bpp, const uint64_t* __restrict__ items,
+                                                 const int64_t* __restrict__ starts) {
     const BParams& bp = *bpp;
-    const int64_t total = starts[NCLS + 1];
-    int64_t cst[NCLS + 2];
-    for (int c = 0; c <= NCLS + 1; ++c) cst[c] = starts[c];
-    for (;;) {
-        unsigned long long base = 0;
-        if (lane_id() == 0) base = atomicAdd(counter, (unsigned long long)chunk);
-        base = __builtin_amdgcn_readfirstlane((int)(base & 0xFFFFFFFFull)) |
-               ((unsigned long long)__builtin_amdgcn_readfirstlane((int)(base >> 32)) << 32);
-        if ((int64_t)base >= total) break;  // every wave leaves once the list is drained
-        const int64_t end = ((int64_t)base + chunk < total) ? (int64_t)base + chunk : total;
-        for (int64_t t = (int64_t)base; t < end; ++t) {
-            const uint64_t g = items[t];
-            int c = 0;
-            for (int k = 1; k <= NCLS; ++k)
-                if ((int64_t)t >= cst[k]) c = k;
-            const int di = find_dom(bp, (int64_t)g);
-            const BDom& D = bp.dom[di];
-            const int64_t node = (int64_t)g - D.first;
-            const int P = D.degree ? (int)D.degree[node] : D.a.P;
-            if (fallback_pass) {
-                if (D.a.status[node] != RBF_ST_FALLBACK) continue;
-                run_class<RBF_PREC_F64>(c, D.a, node, P, lds, 0, 0.0);
-                if (lane_id() == 0 && D.a.status[node] == RBF_ST_OK) D.a.status[node] = RBF_ST_FALLBACK;
-            } else if (PREC == RBF_PREC_F32_IR && c < NCLS && (c & 1)) {
-                // the <= 128 bucket has no float32 solver: the fallback pass
-                // solves it in float64
-                if (lane_id() == 0) D.a.status[node] = RBF_ST_FALLBACK;
-            } else {
-                run_class<PREC>(c, D.a, node, P, lds, max_refine, refine_tol);
-            }
-        }
+    const int64_t beg = starts[BREJECT], end = starts[BREJECT + 1];
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    for (int64_t t = beg + (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE; t < end; t += nw) {
+        const int64_t g = (int64_t)items[t];
+        const BDom& D = bp.dom[find_dom(bp, g)];
+        const int64_t node = g - D.first;
+        const int64_t off = D.a.offsets[node];
+        const int64_t n = D.a.offsets[node + 1] - off;
+        reject_stencil(D.a, node, off, (n < 0 || off < 0 || off + n > D.a.nnz) ? 0 : n, RBF_ST_BADSIZE);
     }
 }
 
@@ -167,11 +102,11 @@ BLayout blayout(int64_t total) {
     L.params = o;
     o += rbf_align(sizeof(BParams));
     L.counts = o;
-    o += rbf_align(sizeof(int) * (NCLS + 2));
+    o += rbf_align(sizeof(int) * (BREJECT + 1));
     L.starts = o;
-    o += rbf_align(sizeof(int64_t) * (NCLS + 2));
+    o += rbf_align(sizeof(int64_t) * (BREJECT + 2));
     L.counter = o;
-    o += rbf_align(sizeof(unsigned long long) * 2);
+    o += rbf_align(sizeof(unsigned long long) * NCOUNTERS);
     L.cls_rank = o;
     o += rbf_align(sizeof(uint32_t) * 2 * total);
     L.items = o;
@@ -188,7 +123,7 @@ rbf_status check_doms(const rbf_domain_desc* doms, int n_doms, int64_t* total) {
         if (!D.X || !D.offsets || !D.idx || !D.w || !D.status || D.N < 1 || D.nnz < 1 || D.n_max < 1) return RBF_EINVAL;
         if (D.d != 2 && D.d != 3) return RBF_EDIM;
         if (D.op_mask == 0 || (D.op_mask & ~0xFu) || (D.d == 2 && (D.op_mask & RBF_OP_DZ))) return RBF_EINVAL;
-        if (!D.degree && (D.degree_uniform < 2 || D.degree_uniform > 4)) return RBF_EUNSUPPORTED;
+        if (!D.degree && (D.degree_uniform < 0 || D.degree_uniform > 4)) return RBF_EUNSUPPORTED;
         if (D.n_max > D.N) return RBF_ETOOFEW;
         t += D.N;
     }
@@ -239,24 +174,27 @@ rbf_status run_batched(rbf_ctx* ctx, const rbf_domain_desc* doms, int n_doms, co
     uint32_t* cls_rank = (uint32_t*)(w + L.cls_rank);
     uint64_t* items = (uint64_t*)(w + L.items);
     RBF_HIP_CHECK(hipMemcpyAsync(dbp, &bp, sizeof(bp), hipMemcpyHostToDevice, s));
-    RBF_HIP_CHECK(hipMemsetAsync(counts, 0, sizeof(int) * (NCLS + 2), s));
+    hipLaunchKernelGGL(k_bzero, dim3(1), dim3(64), 0, s, counts);
     const unsigned nb = (unsigned)((total + 255) / 256);
     hipLaunchKernelGGL(k_bclassify, dim3(nb), dim3(256), 0, s, dbp, counts, cls_rank);
     hipLaunchKernelGGL(k_bscan, dim3(1), dim3(64), 0, s, counts, starts, counter);
     hipLaunchKernelGGL(k_bscatter, dim3(nb), dim3(256), 0, s, dbp, cls_rank, starts, items);
     int cus = 256;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess) cus = prop.multiProcessorCount;
-    const unsigned grid = (unsigned)(cus * waves_per_cu);
-    if (o.precision == RBF_PREC_F64) {
-        hipLaunchKernelGGL((k_bpersist<RBF_PREC_F64>), dim3(grid), dim3(64), 0, s, dbp, items, starts, counter, chunk,
-                           o.max_refine, o.refine_tol, 0);
-    } else {
-        hipLaunchKernelGGL((k_bpersist<RBF_PREC_F32_IR>), dim3(grid), dim3(64), 0, s, dbp, items, starts, counter,
-                           chunk, o.max_refine, o.refine_tol, 0);
-        hipLaunchKernelGGL((k_bpersist<RBF_PREC_F64>), dim3(grid), dim3(64), 0, s, dbp, items, starts, counter + 1,
-                           chunk, o.max_refine, o.refine_tol, 1);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) return RBF_EHIP;
+    const int grid = cus * waves_per_cu;
+    for (int c = 0; c < NBCLS; ++c) {
+        if (!g_bclass[c]) return RBF_EUNSUPPORTED;
+        if (g_bclass[c](dbp, items, starts, counter + c, c, o.precision, chunk, grid, o.max_refine, o.refine_tol, 0,
+                        s) != hipSuccess)
+            return RBF_EHIP;
     }
+    if (o.precision == RBF_PREC_F32_IR)
+        for (int c = 0; c < NBCLS; ++c)
+            if (bcls_maxm(c) <= 64 &&
+                g_bclass[c](dbp, items, starts, counter + NBCLS + c, c, RBF_PREC_F64, chunk, grid, 0, 0.0,
+                            RBF_ST_FALLBACK, s) != hipSuccess)
+                return RBF_EHIP;
+    hipLaunchKernelGGL(k_breject, dim3(64), dim3(256), 0, s, dbp, items, starts);
     RBF_LAUNCH_CHECK();
     return RBF_OK;
 }

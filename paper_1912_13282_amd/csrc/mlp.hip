@@ -712,8 +712,7 @@ __global__ __launch_bounds__(256, 1) void k_surrogate(const float* __restrict__ 
 
 int grid_persistent(int device, int64_t tiles) {
     int cus = 256;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) == hipSuccess) cus = prop.multiProcessorCount;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess) cus = 256;
     const int64_t cap = 2LL * cus;
     return (int)(tiles < cap ? (tiles < 1 ? 1 : tiles) : cap);
 }

@@ -5,34 +5,36 @@
 #pragma once
 
 #include "wsolve.hpp"
+#include "wsolve_quad.hpp"
 
 namespace rbf {
-
-template <int MAXM>
-constexpr int waves_per_block() { return MAXM <= 64 ? 4 : 1; }
-
-template <int MAXM>
-constexpr int row_lds_doubles() {
-    if constexpr (MAXM <= 64) return RowLds<MAXM>::TOTAL;
-    else return big_lds_doubles<MAXM>();
-}
 
 // Plain FP64 solve.  With select != 0 only the stencils whose status equals
 // select (FALLBACK left by the refined form, SURROGATE_REJECTED left by the
 // surrogate) are solved, and a successful solve keeps that status.
 template <int MAXM>
-__global__ __launch_bounds__(MAXM <= 64 ? 256 : 64, MAXM <= 64 ? 3 : 1) void k_weights_f64(StencilArgs a, int64_t N,
-                                                                                        int select) {
-    constexpr int WPB = waves_per_block<MAXM>();
-    __shared__ __attribute__((aligned(16))) double lds[WPB][row_lds_doubles<MAXM>()];
+__global__ __launch_bounds__(256, 3) void k_weights_f64(StencilArgs a, int64_t N, int select) {
+    static_assert(MAXM <= 64, "one row per lane");
+    __shared__ __attribute__((aligned(16))) double lds[4][RowLds<MAXM>::TOTAL];
     const int wv = threadIdx.x / WAVE;
-    const int64_t node = (int64_t)blockIdx.x * WPB + wv;
+    const int64_t node = (int64_t)blockIdx.x * 4 + wv;
     if (node >= N) return;
     // one call site: a second one would duplicate the unrolled solver
     if (select && a.status[node] != select) return;
-    if constexpr (MAXM <= 64) stencil_f64_rows<MAXM, false>(a, node, a.P, lds[wv]);
-    else stencil_f64_big<MAXM>(a, node, a.P, lds[wv]);
+    stencil_f64_rows<MAXM, false>(a, node, a.P, lds[wv]);
     if (select && lane_id() == 0 && a.status[node] == RBF_ST_OK) a.status[node] = (int8_t)select;
+}
+
+// Plain FP64 solve of systems above 64 unknowns: one stencil per 4-wave workgroup.
+template <int MAXM>
+__global__ __launch_bounds__(256, 2) void k_weights_quad(StencilArgs a, int64_t N, int select) {
+    static_assert(MAXM > 64 && MAXM <= 128, "two row groups of 64, two column halves");
+    __shared__ __attribute__((aligned(16))) double lds[QuadLds<MAXM / 2>::TOTAL];
+    const int64_t node = blockIdx.x;
+    if (node >= N) return;
+    if (select && a.status[node] != select) return;  // uniform
+    stencil_f64_quad<MAXM / 2>(a, node, a.P, lds);
+    if (select && threadIdx.x == 0 && a.status[node] == RBF_ST_OK) a.status[node] = (int8_t)select;
 }
 
 // FP32 Gauss-Jordan + FP64 refinement; stencils not accepted are marked FALLBACK.
@@ -51,17 +53,18 @@ using LaunchFn = hipError_t (*)(const StencilArgs&, int64_t, int, int, double, h
 template <int MAXM>
 hipError_t launch_class(const StencilArgs& a, int64_t N, int precision, int max_refine, double refine_tol,
                         hipStream_t s) {
-    constexpr int WPB = waves_per_block<MAXM>();
-    const dim3 grid((unsigned)((N + WPB - 1) / WPB)), block(64 * WPB);
     if constexpr (MAXM > 64) {
         // systems above 64 unknowns are solved in float64 directly; the refined
         // form reports them as FALLBACK (float64 used)
-        hipLaunchKernelGGL((k_weights_f64<MAXM>), grid, block, 0, s, a, N, 0);
-    } else if (precision == RBF_PREC_F64) {
-        hipLaunchKernelGGL((k_weights_f64<MAXM>), grid, block, 0, s, a, N, 0);
+        hipLaunchKernelGGL((k_weights_quad<MAXM>), dim3((unsigned)N), dim3(256), 0, s, a, N, 0);
     } else {
-        hipLaunchKernelGGL((k_weights_ir<MAXM>), grid, block, 0, s, a, N, max_refine, refine_tol);
-        hipLaunchKernelGGL((k_weights_f64<MAXM>), grid, block, 0, s, a, N, RBF_ST_FALLBACK);
+        const dim3 grid((unsigned)((N + 3) / 4)), block(256);
+        if (precision == RBF_PREC_F64) {
+            hipLaunchKernelGGL((k_weights_f64<MAXM>), grid, block, 0, s, a, N, 0);
+        } else {
+            hipLaunchKernelGGL((k_weights_ir<MAXM>), grid, block, 0, s, a, N, max_refine, refine_tol);
+            hipLaunchKernelGGL((k_weights_f64<MAXM>), grid, block, 0, s, a, N, RBF_ST_FALLBACK);
+        }
     }
     return hipGetLastError();
 }
@@ -69,9 +72,10 @@ hipError_t launch_class(const StencilArgs& a, int64_t N, int precision, int max_
 // plain FP64 solve of the stencils whose status equals select
 template <int MAXM>
 hipError_t launch_select(const StencilArgs& a, int64_t N, int select, hipStream_t s) {
-    constexpr int WPB = waves_per_block<MAXM>();
-    hipLaunchKernelGGL((k_weights_f64<MAXM>), dim3((unsigned)((N + WPB - 1) / WPB)), dim3(64 * WPB), 0, s, a, N,
-                       select);
+    if constexpr (MAXM > 64)
+        hipLaunchKernelGGL((k_weights_quad<MAXM>), dim3((unsigned)N), dim3(256), 0, s, a, N, select);
+    else
+        hipLaunchKernelGGL((k_weights_f64<MAXM>), dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, a, N, select);
     return hipGetLastError();
 }
 

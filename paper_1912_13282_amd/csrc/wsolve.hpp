@@ -21,8 +21,7 @@
 //     multipliers in its eliminated columns; corrections replay the recorded
 //     row operations on the float64 residual (K recomputed in float64 from the
 //     scaled offsets kept in LDS).
-//   * n + m in (64, 128]: two rows per lane, LU with partial pivoting and back
-//     substitution in float64 (rows held in private memory).
+//   * n + m in (64, 128]: wsolve_quad.hpp (one stencil on four waves).
 #pragma once
 
 #include "common.hpp"
@@ -594,168 +593,5 @@ __device__ __forceinline__ void stencil_ir_rows(const StencilArgs& a, int64_t no
     }
     store_weights<1>(a, node, off, n, m, F, sol, true, (int8_t)RBF_ST_REFINED);
 }
-
-// --------------------------------------------------- FP64, n + m in (64, 128]
-// Two rows per lane (rows lane and lane + 64), LU with partial pivoting: rows
-// are never swapped, a pivoted row keeps its step number; the right-hand sides
-// are eliminated alongside and the back substitution broadcasts each solved
-// unknown.  The pivot row is read with v_readlane.
-template <int MAXM>
-__device__ __forceinline__ void stencil_f64_big(const StencilArgs& a, int64_t node, int P, double* lds) {
-    static_assert(MAXM > 64 && MAXM <= 128, "two rows per lane");
-    constexpr int RPL = 2;
-    const int lane = lane_id();
-    int64_t off;
-    int n, m;
-    FrameG<RPL> F;
-    if (!stencil_prologue<RPL>(a, node, P, MAXM, off, n, m, F)) return;
-    const int M = n + m;
-    const int d = a.d;
-    const int kpow = a.phs_power;
-    double* xh = lds;  // scaled offsets, 4 doubles per node
-    double row[RPL][MAXM];
-    double rhs[RPL][NR];
-    // assembly: weight rows [q(x_j) | phi(|x_j - x_k|)], polynomial rows
-    // [0 | q_r(x_k)] (evaluated directly), padding rows identity
-#pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-        const int r = lane + 64 * t, j = r - m;
-        if (j >= 0 && j < n) {
-            xh[4 * j] = F.xh[t][0];
-            xh[4 * j + 1] = F.xh[t][1];
-            xh[4 * j + 2] = F.xh[t][2];
-        }
-    }
-    wave_lds_sync();
-    for (int c = 0; c < MAXM; ++c) {
-        const int k = c - m;
-        double xk[3] = {0.0, 0.0, 0.0};
-        if (k >= 0 && k < n) {
-            xk[0] = xh[4 * k];
-            xk[1] = xh[4 * k + 1];
-            xk[2] = xh[4 * k + 2];
-        }
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-            const int r = lane + 64 * t, j = r - m;
-            double v;
-            if (c < m) {
-                v = (j >= 0 && j < n) ? mono(d, c, F.xh[t]) : 0.0;
-            } else if (j >= 0 && j < n) {
-                const double dx = F.xh[t][0] - xk[0], dy = F.xh[t][1] - xk[1], dz = F.xh[t][2] - xk[2];
-                v = (k < n) ? phs_from_r2(dx * dx + dy * dy + dz * dz, kpow) : 0.0;
-            } else if (r < m) {
-                v = (k < n) ? mono(d, r, xk) : 0.0;
-            } else {
-                v = (r == c) ? 1.0 : 0.0;
-            }
-            row[t][c] = v;
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-        const int r = lane + 64 * t, j = r - m;
-#pragma unroll
-        for (int q = 0; q < NR; ++q) rhs[t][q] = 0.0;
-        if (j >= 0 && j < n) {
-            const double r2 = F.xh[t][0] * F.xh[t][0] + F.xh[t][1] * F.xh[t][1] + F.xh[t][2] * F.xh[t][2];
-            const double rr = sqrt(r2);
-            const double pw = (kpow == 5) ? r2 * rr : rr;
-            rhs[t][0] = (double)(kpow * (kpow + d - 2)) * pw;
-#pragma unroll
-            for (int q = 1; q < NR; ++q) rhs[t][q] = (q <= d) ? -(double)kpow * pw * F.xh[t][q - 1] : 0.0;
-        } else if (r < m) {
-#pragma unroll
-            for (int q = 0; q < NR; ++q) rhs[t][q] = mono_lq(d, r, q);
-        }
-    }
-    // LU with partial pivoting, right-hand sides eliminated alongside
-    bool piv[RPL];
-    int step[RPL];
-    double invd[RPL];
-#pragma unroll
-    for (int t = 0; t < RPL; ++t) {
-        piv[t] = (lane + 64 * t) >= MAXM;
-        step[t] = -1;
-        invd[t] = 0.0;
-    }
-    bool ok = true;
-    for (int k = 0; k < M && ok; ++k) {
-        double best = -1.0;
-#pragma unroll
-        for (int t = 0; t < RPL; ++t)
-            if (!piv[t]) best = fmax(best, fabs(row[t][k]));
-        const double mx = wave_max_d(best);
-        if (!(mx > 0.0) || !__builtin_isfinite(mx)) {
-            ok = false;
-            break;
-        }
-        int p, ps = 0;
-        const uint64_t b0 = ballot64(!piv[0] && fabs(row[0][k]) == mx);
-        if (b0) {
-            p = first_lane(b0);
-        } else {
-            p = first_lane(ballot64(!piv[1] && fabs(row[1][k]) == mx));
-            ps = 1;
-        }
-        const double pv = readlane_d(ps == 0 ? row[0][k] : row[1][k], p);
-        const double inv = 1.0 / pv;
-        double l[RPL];
-#pragma unroll
-        for (int t = 0; t < RPL; ++t) {
-            if (lane == p && t == ps) {
-                piv[t] = true;
-                step[t] = k;
-                invd[t] = inv;
-            }
-            l[t] = piv[t] ? 0.0 : row[t][k] * inv;
-            if (!piv[t]) row[t][k] = 0.0;
-        }
-        for (int j = k + 1; j < M; ++j) {
-            const double u = readlane_d(ps == 0 ? row[0][j] : row[1][j], p);
-#pragma unroll
-            for (int t = 0; t < RPL; ++t) row[t][j] = fma(-l[t], u, row[t][j]);
-        }
-#pragma unroll
-        for (int q = 0; q < NR; ++q) {
-            const double u = readlane_d(ps == 0 ? rhs[0][q] : rhs[1][q], p);
-#pragma unroll
-            for (int t = 0; t < RPL; ++t) rhs[t][q] = fma(-l[t], u, rhs[t][q]);
-        }
-    }
-    double sol[RPL][NR];
-#pragma unroll
-    for (int t = 0; t < RPL; ++t)
-#pragma unroll
-        for (int q = 0; q < NR; ++q) sol[t][q] = 0.0;
-    if (ok) {
-        for (int k = M - 1; k >= 0; --k) {
-            int p, ps = 0;
-            const uint64_t b0 = ballot64(step[0] == k);
-            if (b0) {
-                p = first_lane(b0);
-            } else {
-                p = first_lane(ballot64(step[1] == k));
-                ps = 1;
-            }
-#pragma unroll
-            for (int q = 0; q < NR; ++q) {
-                const double y = (ps == 0) ? rhs[0][q] * invd[0] : rhs[1][q] * invd[1];
-                const double xv = readlane_d(y, p);
-#pragma unroll
-                for (int t = 0; t < RPL; ++t) rhs[t][q] = fma(-row[t][k], xv, rhs[t][q]);
-                if (lane == (k & 63)) {
-                    if (k < 64) sol[0][q] = xv;
-                    else sol[1][q] = xv;
-                }
-            }
-        }
-    }
-    const bool good = ok && repro_check<RPL>(a, n, m, F, sol);
-    store_weights<RPL>(a, node, off, n, m, F, sol, good, (int8_t)RBF_ST_OK);
-}
-
-template <int MAXM>
-constexpr int big_lds_doubles() { return 4 * MAXM; }
 
 }  // namespace rbf

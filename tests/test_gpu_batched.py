@@ -103,3 +103,24 @@ def test_large_systems_parity(gpu, precision):
     E = scaled_err(w.cpu().numpy(), wo, ops, off, nd.h)
     print(f"  N={nd.N} E={E:.2e}", flush=True)
     assert E <= 1e-10
+
+
+@pytest.mark.parametrize("n,P", [(59, 2), (91, 4), (113, 4)])
+def test_large_systems_sizes_2d(gpu, n, P):
+    """2D systems of 65, 106 and 128 unknowns (the edges of the four-wave solver's range)."""
+    nd = ns.disk(0.07, 1007)
+    off = ns.offsets_from_sizes(np.full(nd.N, n, np.int64))
+    Xd, od = torch.from_numpy(nd.X).to(gpu), torch.from_numpy(off).to(gpu)
+    idx = rb.select_stencils(Xd, od, n)
+    ops = ("lap", "dx", "dy")
+    w, st = rb.compute_weights(Xd, od, idx, n, P, ops, precision="f64")
+    torch.cuda.synchronize()
+    wo, sto = orbf.weights(nd.X, off, idx.cpu().numpy(), P, ops)
+    st = st.cpu().numpy()
+    good = np.nonzero(sto == 0)[0]
+    assert good.size >= 0.99 * nd.N and np.all(st[good] == 0)
+    pos = np.concatenate([np.arange(off[i], off[i + 1]) for i in good])
+    offg = ns.offsets_from_sizes(np.full(good.size, n, np.int64))
+    E = scaled_err(w.cpu().numpy()[:, pos], wo[:, pos], ops, offg, nd.h[good])
+    print(f"  N={nd.N} M={n + (6 if P == 2 else 15)} E={E:.2e}", flush=True)
+    assert E <= 1e-10
