@@ -43,6 +43,59 @@ __device__ __forceinline__ int find_dom(const BParams& bp, int64_t g) {
 }
 
 
+// The persistent loops call the solvers through these non-inlined functions:
+// register allocation across a loop around a fully unrolled solver spills
+// heavily, while a call keeps the solver's allocation separate.  The stencil
+// arguments are re-made uniform (scalar registers) inside the callee, and each
+// callee owns its LDS.
+template <typename T>
+__device__ __forceinline__ T* rfl_ptr(T* p) {
+    const uint64_t v = (uint64_t)p;
+    return (T*)((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(v & 0xFFFFFFFFu)) |
+                ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32));
+}
+__device__ __forceinline__ int rfl(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t rfl64(int64_t v) {
+    return (int64_t)((uint64_t)(uint32_t)rfl((int)(v & 0xFFFFFFFF)) | ((uint64_t)(uint32_t)rfl((int)(v >> 32)) << 32));
+}
+__device__ __forceinline__ double rfld(double v) { return __hiloint2double(rfl(__double2hiint(v)), rfl(__double2loint(v))); }
+
+__device__ __forceinline__ StencilArgs uniform_args(const StencilArgs& a0) {
+    StencilArgs a;
+    a.X = rfl_ptr(a0.X);
+    a.N = rfl64(a0.N);
+    a.d = rfl(a0.d);
+    a.P = rfl(a0.P);
+    a.offsets = rfl_ptr(a0.offsets);
+    a.idx = rfl_ptr(a0.idx);
+    a.nnz = rfl64(a0.nnz);
+    a.n_max = rfl(a0.n_max);
+    a.op_mask = (unsigned)rfl((int)a0.op_mask);
+    a.phs_power = rfl(a0.phs_power);
+    a.scale_mode = rfl(a0.scale_mode);
+    a.repro_tol = rfld(a0.repro_tol);
+    a.w = rfl_ptr(a0.w);
+    a.status = rfl_ptr(a0.status);
+    return a;
+}
+
+template <int PREC, int MAXM>
+__device__ __attribute__((noinline)) void solve_item_rows(StencilArgs a0, int64_t node, int P, int max_refine,
+                                                          double refine_tol) {
+    __shared__ __attribute__((aligned(16))) double lds[RowLds<MAXM>::TOTAL];
+    const StencilArgs a = uniform_args(a0);
+    if constexpr (PREC == RBF_PREC_F64)
+        stencil_f64_rows<MAXM, true>(a, rfl64(node), rfl(P), lds);
+    else
+        stencil_ir_rows<MAXM, true>(a, rfl64(node), rfl(P), lds, rfl(max_refine), rfld(refine_tol));
+}
+
+template <int H>
+__device__ __attribute__((noinline)) void solve_item_quad(StencilArgs a0, int64_t node, int P) {
+    __shared__ __attribute__((aligned(16))) double lds[QuadLds<H>::TOTAL];
+    stencil_f64_quad<H>(uniform_args(a0), rfl64(node), rfl(P), lds);
+}
+
 // Persistent solve of size class `cls` (items starts[cls] .. starts[cls+1]).
 // select != 0: only items whose status equals select are solved (the FP64 pass
 // over the refined form's fallbacks) and keep that status.
@@ -51,7 +104,6 @@ __global__ __launch_bounds__(64, MAXM <= 32 ? 4 : (MAXM <= 48 ? 3 : 2)) void k_b
     const BParams* __restrict__ bpp, const uint64_t* __restrict__ items, const int64_t* __restrict__ starts,
     unsigned long long* __restrict__ counter, int cls, int chunk, int max_refine, double refine_tol, int select) {
     static_assert(MAXM <= 64, "one row per lane");
-    __shared__ __attribute__((aligned(16))) double lds[RowLds<MAXM>::TOTAL];
     const BParams& bp = *bpp;
     const int64_t beg = starts[cls], end = starts[cls + 1];
     for (;;) {
@@ -68,11 +120,7 @@ __global__ __launch_bounds__(64, MAXM <= 32 ? 4 : (MAXM <= 48 ? 3 : 2)) void k_b
             const int64_t node = g - D.first;
             if (select && D.a.status[node] != select) continue;
             const int P = D.degree ? (int)D.degree[node] : D.a.P;
-            if constexpr (PREC == RBF_PREC_F64) {
-                stencil_f64_rows<MAXM, true>(D.a, node, P, lds);
-            } else {
-                stencil_ir_rows<MAXM, true>(D.a, node, P, lds, max_refine, refine_tol);
-            }
+            solve_item_rows<PREC, MAXM>(D.a, node, P, max_refine, refine_tol);
             if (select && lane_id() == 0 && D.a.status[node] == RBF_ST_OK) D.a.status[node] = (int8_t)select;
         }
     }
@@ -81,20 +129,25 @@ __global__ __launch_bounds__(64, MAXM <= 32 ? 4 : (MAXM <= 48 ? 3 : 2)) void k_b
 // Persistent solve of the class above 64 unknowns: 4-wave workgroups, one
 // stencil at a time per workgroup (float64; the refined form reports FALLBACK).
 template <int PREC, int MAXM>
-__global__ __launch_bounds__(256, 2) void k_bclass_quad(const BParams* __restrict__ bpp,
+__global__ __launch_bounds__(256, 3) void k_bclass_quad(const BParams* __restrict__ bpp,
                                                         const uint64_t* __restrict__ items,
                                                         const int64_t* __restrict__ starts,
                                                         unsigned long long* __restrict__ counter, int cls, int chunk,
                                                         int select) {
     static_assert(MAXM > 64 && MAXM <= 128, "two row groups of 64, two column halves");
-    __shared__ __attribute__((aligned(16))) double lds[QuadLds<MAXM / 2>::TOTAL];
     __shared__ unsigned long long grab;
     const BParams& bp = *bpp;
     const int64_t beg = starts[cls], end = starts[cls + 1];
     for (;;) {
         if (threadIdx.x == 0) grab = atomicAdd(counter, (unsigned long long)chunk);
         __syncthreads();
-        const int64_t t0 = beg + (int64_t)grab;
+        // uniform by construction; readfirstlane lets the compiler know, so every
+        // value derived from the item stays in scalar registers
+        const unsigned long long gv = grab;
+        const int64_t t0 = beg + (int64_t)((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane(
+                                               (int)(gv & 0xFFFFFFFFull)) |
+                                           ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane(
+                                                (int)(gv >> 32)) << 32));
         __syncthreads();  // every thread has read grab before it is written again
         if (t0 >= end) break;  // uniform: the whole workgroup leaves once the class is drained
         const int64_t t1 = (t0 + chunk < end) ? t0 + chunk : end;
@@ -104,7 +157,7 @@ __global__ __launch_bounds__(256, 2) void k_bclass_quad(const BParams* __restric
             const int64_t node = g - D.first;
             if (select && D.a.status[node] != select) continue;
             const int P = D.degree ? (int)D.degree[node] : D.a.P;
-            stencil_f64_quad<MAXM / 2>(D.a, node, P, lds);
+            solve_item_quad<MAXM / 2>(D.a, node, P);
             if (threadIdx.x == 0 && D.a.status[node] == RBF_ST_OK) {
                 if (PREC == RBF_PREC_F32_IR) D.a.status[node] = RBF_ST_FALLBACK;
                 else if (select) D.a.status[node] = (int8_t)select;

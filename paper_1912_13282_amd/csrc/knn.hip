@@ -31,6 +31,11 @@ struct GridParams {
 constexpr int BBOX_BLOCKS = 512;
 constexpr int SCAN_CHUNK = 1024;  // elements per scan block (256 threads x 4)
 
+__global__ __launch_bounds__(256) void k_zero_ints(int* __restrict__ p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 __global__ __launch_bounds__(256) void k_bbox_partial(const double* __restrict__ X, int64_t N, int d,
                                                       double* __restrict__ part) {
     __shared__ double sm[4][6];
@@ -521,7 +526,9 @@ extern "C" rbf_status rbf_select_stencils(rbf_ctx* ctx, const double* X, int64_t
     int nbb = (int)std::min<int64_t>(BBOX_BLOCKS, (N + 255) / 256);
     hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(256), 0, s, X, N, d, part);
     hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(64), 0, s, part, nbb, N, d, target, L.cap, gp);
-    RBF_HIP_CHECK(hipMemsetAsync(count, 0, sizeof(int) * (L.cap + 1), s));
+    // cleared by a kernel (a memset node in a captured graph is not reliable)
+    hipLaunchKernelGGL(k_zero_ints, dim3((unsigned)((L.cap + 1 + 255) / 256)), dim3(256), 0, s, count,
+                       (int64_t)L.cap + 1);
     int nbN = (int)((N + 255) / 256);
     hipLaunchKernelGGL(k_bin_count, dim3(nbN), dim3(256), 0, s, X, N, d, gp, count, cell_of, rank);
     hipLaunchKernelGGL(k_scan_blocks, dim3(L.nb_scan), dim3(256), 0, s, count, L.cap + 1, bsum);

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(256, 3) void k_weights_f64(StencilArgs a, int64_t N
 
 // Plain FP64 solve of systems above 64 unknowns: one stencil per 4-wave workgroup.
 template <int MAXM>
-__global__ __launch_bounds__(256, 2) void k_weights_quad(StencilArgs a, int64_t N, int select) {
+__global__ __launch_bounds__(256, 3) void k_weights_quad(StencilArgs a, int64_t N, int select) {
     static_assert(MAXM > 64 && MAXM <= 128, "two row groups of 64, two column halves");
     __shared__ __attribute__((aligned(16))) double lds[QuadLds<MAXM / 2>::TOTAL];
     const int64_t node = blockIdx.x;

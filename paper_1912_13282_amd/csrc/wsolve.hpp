@@ -464,6 +464,26 @@ __device__ __forceinline__ void stencil_f64_rows(const StencilArgs& a, int64_t n
     store_weights<1>(a, node, off, n, m, F, sol, good, (int8_t)RBF_ST_OK);
 }
 
+// float64 right-hand sides of this lane's row (as assemble_row)
+__device__ __forceinline__ void rhs_row(const StencilArgs& a, const FrameG<1>& F, int n, int m, double (&rhs)[NR]) {
+    const int d = a.d, kpow = a.phs_power;
+    const int r = lane_id();
+    const bool wrow = r >= m && r < m + n;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) rhs[q] = 0.0;
+    if (wrow) {
+        const double r2 = F.xh[0][0] * F.xh[0][0] + F.xh[0][1] * F.xh[0][1] + F.xh[0][2] * F.xh[0][2];
+        const double rr = sqrt(r2);
+        const double pw = (kpow == 5) ? r2 * rr : rr;  // ||x_j||^(k-2)
+        rhs[0] = (double)(kpow * (kpow + d - 2)) * pw;
+#pragma unroll
+        for (int q = 1; q < NR; ++q) rhs[q] = (q <= d) ? -(double)kpow * pw * F.xh[0][q - 1] : 0.0;
+    } else if (r < m) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) rhs[q] = mono_lq(d, r, q);
+    }
+}
+
 // ------------------------------------------------------- FP32 + refine (<= 64)
 // Acceptance: every right-hand side satisfies
 //     max|r| <= tol * ||K||_inf * max|x|,  tol = max(sqrt(M) 2^-53, refine_tol)
@@ -487,16 +507,21 @@ __device__ __forceinline__ void stencil_ir_rows(const StencilArgs& a, int64_t no
     float* prow = reinterpret_cast<float*>(lds + L::o_f32);
     float* sol32 = prow + 2 * L::PRWF;
 
-    double B[NR];
     float row[MAXM];
-    assemble_row<MAXM, float>(a, F, n, m, lds, row, B);
     float b32[NR];
+    {
+        double B0[NR];
+        assemble_row<MAXM, float>(a, F, n, m, lds, row, B0);
 #pragma unroll
-    for (int q = 0; q < NR; ++q) b32[q] = (float)B[q];
+        for (int q = 0; q < NR; ++q) b32[q] = (float)B0[q];
+    }
     float s32[NR];
     int mystep;
     float invd;
     const bool ok32 = gauss_jordan<float, MAXM, GUARD>(row, b32, prow, sol32, s32, true, mystep, invd, M);
+    // the float64 right-hand side again (cheaper than keeping it live through the elimination)
+    double B[NR];
+    rhs_row(a, F, n, m, B);
 
     bool accepted = false;
     double x[NR];
