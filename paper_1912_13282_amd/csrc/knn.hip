@@ -29,6 +29,11 @@ struct GridParams {
 };
 
 constexpr int BBOX_BLOCKS = 512;
+// mean nodes per cell relative to n_max / (unit-ball volume), i.e. the cell side
+// relative to the stencil radius (measured: 2D is fastest at about one stencil
+// radius per cell, 3D at half the volume, which cuts the 27-cell candidate set)
+constexpr double CELL_FILL_2D = 1.0;
+constexpr double CELL_FILL_3D = 0.5;
 constexpr int SCAN_CHUNK = 1024;  // elements per scan block (256 threads x 4)
 
 __global__ __launch_bounds__(256) void k_zero_ints(int* __restrict__ p, int64_t n) {
@@ -321,10 +326,18 @@ __device__ __forceinline__ int lin3(const GridParams& g, int x, int y, int z) {
     return x + g.dims[0] * (y + g.dims[1] * z);
 }
 
-// candidate range of slot s of ring R (rows of cells along x; see file header)
+// gap between coordinate q and the cells lo..hi along axis a (0 inside)
+__device__ __forceinline__ double axis_gap(const GridParams& g, double q, int lo, int hi, int a) {
+    const double blo = g.origin[a] + lo * g.cell, bhi = g.origin[a] + (hi + 1) * g.cell;
+    return q < blo ? blo - q : (q > bhi ? q - bhi : 0.0);
+}
+
+// candidate range of slot s of ring R (rows of cells along x; see file header).
+// A slot whose cells all lie farther than the current k-th key wk is empty: every
+// node in it has a larger key (the relative margin covers rounding).
 __device__ __forceinline__ void slot_range(const GridParams& g, const int* __restrict__ cell_start, int d,
-                                           const int (&qc)[3], int R, bool first, int s, int nslots,
-                                           int& start, int& len) {
+                                           const int (&qc)[3], const double (&qx)[3], double wk, int R, bool first,
+                                           int s, int nslots, int& start, int& len) {
     start = 0;
     len = 0;
     if (s >= nslots) return;
@@ -344,6 +357,11 @@ __device__ __forceinline__ void slot_range(const GridParams& g, const int* __res
         int cx = side ? qc[0] + R : qc[0] - R;
         if (cx < 0 || cx >= g.dims[0]) return;
         xlo = xhi = cx;
+    }
+    if (!first) {
+        const double gx = axis_gap(g, qx[0], xlo, xhi, 0), gy = axis_gap(g, qx[1], cy, cy, 1);
+        const double gz = (d == 3) ? axis_gap(g, qx[2], cz, cz, 2) : 0.0;
+        if ((gx * gx + gy * gy + gz * gz) * (1.0 - 1e-9) > wk) return;
     }
     int a = cell_start[lin3(g, xlo, cy, cz)];
     int b = cell_start[lin3(g, xhi, cy, cz) + 1];
@@ -398,7 +416,7 @@ __global__ __launch_bounds__(256) void k_knn(const GridParams* __restrict__ gpp,
         const int nslots = 2 * ((d == 3) ? W * W : W);
         for (int g0 = 0; g0 < nslots; g0 += WAVE) {
             int st, ln;
-            slot_range(g, cell_start, d, qc, R, first, g0 + lane, nslots, st, ln);
+            slot_range(g, cell_start, d, qc, qx, wk, R, first, g0 + lane, nslots, st, ln);
             int incl = ln;
 #pragma unroll
             for (int o = 1; o < WAVE; o <<= 1) {
@@ -521,7 +539,7 @@ extern "C" rbf_status rbf_select_stencils(rbf_ctx* ctx, const double* X, int64_t
     hipStream_t s = ctx->stream;
 
     const double unit_ball = (d == 2) ? M_PI : 4.0 * M_PI / 3.0;
-    const double target = fmax(1.0, (double)n_max / unit_ball);
+    const double target = fmax(1.0, ((d == 3) ? CELL_FILL_3D : CELL_FILL_2D) * (double)n_max / unit_ball);
 
     int nbb = (int)std::min<int64_t>(BBOX_BLOCKS, (N + 255) / 256);
     hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(256), 0, s, X, N, d, part);
