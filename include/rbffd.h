@@ -204,8 +204,8 @@ rbf_status rbf_get_plan(const rbf_ctx* ctx, rbf_plan* plan);
  * second block row of that system (polynomial reproduction), which the plain
  * weights satisfy exactly.
  *
- * Network: 30 -> 128 -> 128 -> 128 -> 15, exact-erf GELU after the hidden
- * layers.  Input: the scaled offsets (x_j - x_i)/s, s = max_j |x_j - x_i|,
+ * Network: 30 -> 128 -> 128 -> 128 -> 15, erf-GELU after the hidden layers
+ * (erf by Abramowitz & Stegun 7.1.26, |error| <= 1.5e-7).  Input: the scaled offsets (x_j - x_i)/s, s = max_j |x_j - x_i|,
  * in stencil order (x, y interleaved, the centre's zeros included), in the
  * canonical frame of the stencil: rotated so that node 1 lies on +x, then
  * y reflected so that node 2 has y >= 0 (float64, c = o_1x/|o_1|,

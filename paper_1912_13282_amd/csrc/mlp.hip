@@ -1,6 +1,6 @@
 // Learned surrogate of the 2D, 15-node Laplacian RBF-FD weights.
 //
-// Network 30 -> 128 -> 128 -> 128 -> 15 (GELU), inputs the scaled stencil
+// Network 30 -> 128 -> 128 -> 128 -> 15 (erf-GELU), inputs the scaled stencil
 // offsets (x_j - x_i)/s in stencil order and in a canonical frame (rotation
 // and reflection, under which the Laplacian weights do not change), outputs
 // the scaled weights w_j s^2.
@@ -74,10 +74,35 @@ __device__ __forceinline__ f32x4 zero4() {
     return z;
 }
 
-// exact erf form: g(z) = z Phi(z), g'(z) = Phi(z) + z phi(z)
-__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+// erf-GELU g(z) = z Phi(z), Phi(z) = (1 + erf(z / sqrt 2)) / 2, g'(z) = Phi(z) + z phi(z).
+// erf from Abramowitz & Stegun 7.1.26 (Hastings' rational approximation,
+// |error| <= 1.5e-7): for u >= 0, 1 - erf(u) = t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) e^(-u^2),
+// t = 1 / (1 + p u).  Phi comes straight from this tail form (no cancellation for
+// negative z), and phi reuses the same exponential e^(-z^2/2).
+struct PhiPair {
+    float Phi, phi;
+};
+__device__ __forceinline__ PhiPair normal_cdf_pdf(float z) {
+    const float u = fabsf(z) * 0.70710678118654752f;
+    const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, u, 1.0f));
+    const float poly =
+        t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, 1.061405429f, -1.453152027f), 1.421413741f), -0.284496736f), 0.254829592f);
+    const float e = __builtin_amdgcn_exp2f(-u * u * 1.44269504088896341f);  // e^(-u^2) = e^(-z^2/2)
+    const float tail = 0.5f * poly * e;                                     // 1 - Phi(|z|)
+    PhiPair r;
+    r.Phi = (z >= 0.0f) ? 1.0f - tail : tail;
+    r.phi = 0.39894228040143268f * e;
+    return r;
+}
+__device__ __forceinline__ float gelu(float z) { return z * normal_cdf_pdf(z).Phi; }
 __device__ __forceinline__ float gelu_prime(float z) {
-    return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+    const PhiPair p = normal_cdf_pdf(z);
+    return p.Phi + z * p.phi;
+}
+__device__ __forceinline__ void gelu_both(float z, float& g, float& gp) {
+    const PhiPair p = normal_cdf_pdf(z);
+    g = z * p.Phi;
+    gp = p.Phi + z * p.phi;
 }
 
 // feature index held in slot j of lane group g of k block kb (hidden layers)
@@ -141,8 +166,15 @@ __device__ __forceinline__ void hidden_layer(const bf16x8* tiles, const float* _
 #pragma unroll
             for (int ct = 0; ct < NCT; ++ct) {
                 const float z = acc[ct][r] + b;
-                if constexpr (GRAD) gp[ot][ct][r] = gelu_prime(z);
-                ou[ot >> 1][ct][(ot & 1) * 4 + r] = bf16_bits(gelu(z));
+                float gz;
+                if constexpr (GRAD) {
+                    float gpz;
+                    gelu_both(z, gz, gpz);
+                    gp[ot][ct][r] = gpz;
+                } else {
+                    gz = gelu(z);
+                }
+                ou[ot >> 1][ct][(ot & 1) * 4 + r] = bf16_bits(gz);
             }
         }
         // keep each tile's operand loads next to their use (bounds register pressure)
@@ -516,7 +548,7 @@ __device__ __forceinline__ double xor16_32_sum(double v) {
     return v;
 }
 
-__global__ __launch_bounds__(256, 1) void k_surrogate(const float* __restrict__ params,
+__global__ __launch_bounds__(256, 2) void k_surrogate(const float* __restrict__ params,
                                                       const bf16x8* __restrict__ packed, const double* __restrict__ X,
                                                       int64_t N, const int64_t* __restrict__ offsets,
                                                       const int32_t* __restrict__ idx, int64_t nnz, double tol,
@@ -614,11 +646,11 @@ __global__ __launch_bounds__(256, 1) void k_surrogate(const float* __restrict__ 
             }
             r2 = fmax(r2, __shfl_xor(r2, 16));
             r2 = fmax(r2, __shfl_xor(r2, 32));
-            const double sc = sqrt(r2);
+            const double sc = sqrt(r2), isc = 1.0 / sc;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const bool live = 4 * g + r < NODES;
-                const double xh = q[r][1] / sc, yh = q[r][2] / sc;
+                const double xh = q[r][1] * isc, yh = q[r][2] * isc;
                 q[r][0] = live ? 1.0 : 0.0;
                 q[r][1] = xh;
                 q[r][2] = yh;
@@ -642,22 +674,22 @@ __global__ __launch_bounds__(256, 1) void k_surrogate(const float* __restrict__ 
                     G[a][bb] = xor16_32_sum(t2);
                 }
             }
-            // Cholesky G = L L^T (L stored in the lower triangle of G)
+            // Cholesky G = L L^T (L stored in the lower triangle of G, 1/L_kk kept)
             bool spd = true;
+            double il[6];
 #pragma unroll
             for (int k = 0; k < 6; ++k) {
                 double dkk = G[k][k];
 #pragma unroll
                 for (int p = 0; p < k; ++p) dkk -= G[k][p] * G[k][p];
                 spd = spd && dkk > 0.0;
-                const double lkk = sqrt(spd ? dkk : 1.0);
-                G[k][k] = lkk;
+                il[k] = 1.0 / sqrt(spd ? dkk : 1.0);
 #pragma unroll
                 for (int i2 = k + 1; i2 < 6; ++i2) {
                     double t = G[k][i2];
 #pragma unroll
                     for (int p = 0; p < k; ++p) t -= G[i2][p] * G[k][p];
-                    G[i2][k] = t / lkk;
+                    G[i2][k] = t * il[k];
                 }
             }
             // rhs = l_q - Q^T y; solve L z = rhs, L^T cvec = z
@@ -668,14 +700,14 @@ __global__ __launch_bounds__(256, 1) void k_surrogate(const float* __restrict__ 
                 double t = lq[k] - u[k];
 #pragma unroll
                 for (int p = 0; p < k; ++p) t -= G[k][p] * cv[p];
-                cv[k] = t / G[k][k];
+                cv[k] = t * il[k];
             }
 #pragma unroll
             for (int k = 5; k >= 0; --k) {
                 double t = cv[k];
 #pragma unroll
                 for (int p = k + 1; p < 6; ++p) t -= G[p][k] * cv[p];
-                cv[k] = t / G[k][k];
+                cv[k] = t * il[k];
             }
             double wl[4];
 #pragma unroll
@@ -700,10 +732,10 @@ __global__ __launch_bounds__(256, 1) void k_surrogate(const float* __restrict__ 
             rho /= 2.0;  // max(1, max |l_q|)
             const bool accept = spd && finite && rho <= tol;
             if (accept) {
-                const double s2 = sc * sc;
+                const double is2 = isc * isc;
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    if (4 * g + r < NODES) w[off + 4 * g + r] = wl[r] / s2;
+                    if (4 * g + r < NODES) w[off + 4 * g + r] = wl[r] * is2;
             }
             if (g == 0) status[i] = accept ? RBF_ST_SURROGATE : RBF_ST_SURROGATE_REJECTED;
         }
