@@ -20,21 +20,34 @@ __global__ __launch_bounds__(256) void k_csr_rows(int64_t N, const int64_t* __re
                                                   const int32_t* __restrict__ idx, const double* __restrict__ w,
                                                   int n_ops, int64_t nnz, int n_max, int32_t* __restrict__ col,
                                                   double* __restrict__ vals) {
+    constexpr int S = G * E;
+    // the row's weights in stencil order, staged so that the sorted order can
+    // be gathered without a second pass over global memory
+    __shared__ double sw[256 / G][4][S];
     const int lane = lane_id();
     const int gl = lane & (G - 1);
+    const int rib = threadIdx.x / G;
     const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
     if (row >= N) return;  // whole groups leave together (G divides 64)
     const int64_t off = offsets[row];
     const int64_t n64 = offsets[row + 1] - off;
     const int n = (n64 < 0 || n64 > n_max) ? 0 : (int)n64;
     int key[E], pos[E];
+    double wv[4][E];
 #pragma unroll
     for (int s = 0; s < E; ++s) {
         const int e = gl + G * s;
         pos[s] = e;
         key[s] = (e < n) ? idx[off + e] : 0x7FFFFFFF;
     }
-    constexpr int S = G * E;
+    // issued before the sort so that the loads are in flight during it
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            const int e = gl + G * s;
+            wv[r][s] = (r < n_ops && e < n) ? w[r * nnz + off + e] : 0.0;
+        }
 #pragma unroll
     for (int k = 2; k <= S; k <<= 1) {
 #pragma unroll
@@ -78,11 +91,18 @@ __global__ __launch_bounds__(256) void k_csr_rows(int64_t N, const int64_t* __re
         }
     }
 #pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int s = 0; s < E; ++s) sw[rib][r][gl + G * s] = wv[r][s];
+    wave_lds_sync();  // the group lies inside one wavefront
+#pragma unroll
     for (int s = 0; s < E; ++s) {
         const int e = gl + G * s;
         if (e < n) {
             col[off + e] = key[s];
-            for (int r = 0; r < n_ops; ++r) vals[r * nnz + off + e] = w[r * nnz + off + pos[s]];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (r < n_ops) vals[r * nnz + off + e] = sw[rib][r][pos[s]];
         }
     }
     (void)lane;
