@@ -107,3 +107,48 @@ def test_mlp_parameter_layout():
     for k in p:
         assert torch.equal(back[k], p[k])
     assert flat[0] == 0 and flat[128 * 30] == 1 and flat[-1] == 7
+
+
+def test_defaults_and_status_strings(lib_path):
+    import ctypes
+    from paper_1912_13282_amd import _binding as B
+    L = ctypes.CDLL(lib_path)
+    o = B.rbf_options()
+    assert L.rbf_options_default(ctypes.byref(o)) == 0
+    assert (o.precision, o.max_refine, o.phs_power, o.scale_mode) == (0, 10, 3, 0)
+    assert (o.repro_tol, o.refine_tol, o.surrogate_tol) == (1e-8, 0.0, 1e-6)
+    L.rbf_status_string.restype = ctypes.c_char_p
+    texts = {c: L.rbf_status_string(c) for c in (0, -1, -2, -3, -4, -5, -6, -7)}
+    assert len(set(texts.values())) == 8 and texts[-7] == b"unknown status"
+
+
+def test_more_host_argument_errors_without_gpu(lib_path):
+    """Every entry point rejects a missing context or inconsistent sizes on the host."""
+    import ctypes
+    from paper_1912_13282_amd import _binding as B
+    L = ctypes.CDLL(lib_path)
+    b = ctypes.c_size_t()
+    # batched: domain count outside [1, 16], missing arrays
+    D = (B.rbf_domain_desc * 17)()
+    assert L.rbf_batched_workspace(D, 0, ctypes.byref(b)) == -1
+    assert L.rbf_batched_workspace(D, 17, ctypes.byref(b)) == -1
+    assert L.rbf_batched_workspace(D, 1, ctypes.byref(b)) == -1          # X, offsets... are NULL
+    D[0].X = D[0].offsets = D[0].idx = D[0].w = D[0].status = ctypes.c_void_p(16)
+    D[0].N, D[0].nnz, D[0].n_max, D[0].d, D[0].op_mask, D[0].degree_uniform = 100, 1500, 15, 4, 1, 2
+    assert L.rbf_batched_workspace(D, 1, ctypes.byref(b)) == -3          # EDIM
+    D[0].d = 2
+    D[0].degree_uniform = 5
+    assert L.rbf_batched_workspace(D, 1, ctypes.byref(b)) == -6          # degree beyond 4
+    D[0].degree_uniform = 2
+    D[0].n_max = 101
+    assert L.rbf_batched_workspace(D, 1, ctypes.byref(b)) == -2          # ETOOFEW
+    D[0].n_max = 15
+    assert L.rbf_batched_workspace(D, 1, ctypes.byref(b)) == 0 and b.value >= 100 * 16
+    assert L.rbf_compute_weights_batched(None, D, 1, None, None, ctypes.c_size_t(0)) == -1
+    # surrogate and MLP entry points
+    assert L.rbf_mlp_grad_workspace(ctypes.c_int64(0), ctypes.byref(b)) == -1
+    assert L.rbf_mlp_grad_workspace(ctypes.c_int64(130), ctypes.byref(b)) == 0 and b.value == 3 * 38976 * 4
+    assert L.rbf_mlp_pack(None, None, None) == -1
+    assert L.rbf_surrogate_load(None, None) == -1
+    assert L.rbf_assemble_csr(None, ctypes.c_int64(1), None, None, None, 0, ctypes.c_int64(1), 1, None, None,
+                              None) == -1

@@ -124,3 +124,51 @@ def test_large_systems_sizes_2d(gpu, n, P):
     E = scaled_err(w.cpu().numpy()[:, pos], wo[:, pos], ops, offg, nd.h[good])
     print(f"  N={nd.N} M={n + (6 if P == 2 else 15)} E={E:.2e}", flush=True)
     assert E <= 1e-10
+
+
+@pytest.mark.parametrize("P", [0, 1, 2, 4])
+def test_batched_uniform_degree_matches_per_call(gpu, P):
+    """Domains with a uniform degree (no per-node array), 2D and 3D in one batch: the
+    batched weights equal the per-call weights and the oracle."""
+    nd2 = ns.disk(0.05, 1011)
+    nd3 = ns.cube_minus_sphere(1.0 / 12, 1012)
+    doms, ref = [], []
+    for nd, n0 in ((nd2, 14), (nd3, 30)):
+        n = max(n0, -(-3 * ns.n_monomials(nd.d, P) // 2))  # at least 1.5 m (3D degree 4: 53 + 35 unknowns)
+        off = ns.offsets_from_sizes(np.full(nd.N, n, np.int64))
+        Xd, od = torch.from_numpy(nd.X).to(gpu), torch.from_numpy(off).to(gpu)
+        idx = rb.select_stencils(Xd, od, n)
+        ops = ("lap", "dx", "dy") + (("dz",) if nd.d == 3 else ())
+        doms.append(rb.Domain(Xd, od, idx, n, P, ops))
+        w1, s1 = rb.compute_weights(Xd, od, idx, n, P, ops, precision="f64")
+        ref.append((nd, off, ops, w1, s1))
+    rb.compute_weights_batched(doms, precision="f64")
+    torch.cuda.synchronize()
+    for D, (nd, off, ops, w1, s1) in zip(doms, ref):
+        st = D.status.cpu().numpy()
+        assert np.array_equal(st, s1.cpu().numpy())
+        wo, sto = orbf.weights(nd.X, off, D.idx.cpu().numpy(), P, ops)
+        good = np.nonzero((st == 0) & (sto == 0))[0]
+        assert good.size >= 0.9 * nd.N
+        pos = np.concatenate([np.arange(off[i], off[i + 1]) for i in good])
+        offg = ns.offsets_from_sizes(np.diff(off)[good])
+        E = scaled_err(D.w.cpu().numpy()[:, pos], wo[:, pos], ops, offg, nd.h[good])
+        E1 = scaled_err(D.w.cpu().numpy()[:, pos], w1.cpu().numpy()[:, pos], ops, offg, nd.h[good])
+        print(f"  d={nd.d} P={P}: vs oracle {E:.1e}, vs per-call {E1:.1e}", flush=True)
+        assert E <= 1e-10 and E1 <= 1e-12
+
+
+def test_batched_phs5(gpu):
+    doms, ref = build_batch(gpu, per_domain=500)
+    rb.compute_weights_batched(doms, precision="f64", phs_power=5)
+    torch.cuda.synchronize()
+    for D, (nd, P, off, ops) in zip(doms, ref):
+        wo, sto = orbf.weights(nd.X, off, D.idx.cpu().numpy(), P.astype(np.int64), ops, phs_power=5)
+        st = D.status.cpu().numpy()
+        good = np.nonzero((st == 0) & (sto == 0))[0]
+        assert good.size >= 0.98 * nd.N
+        pos = np.concatenate([np.arange(off[i], off[i + 1]) for i in good])
+        offg = ns.offsets_from_sizes(np.diff(off)[good])
+        E = scaled_err(D.w.cpu().numpy()[:, pos], wo[:, pos], ops, offg, nd.h[good])
+        print(f"  {nd.meta['domain']} r^5: E = {E:.1e}", flush=True)
+        assert E <= 1e-10
