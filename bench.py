@@ -17,6 +17,9 @@ Other workloads (the same JSON contract, one line each):
            plain FP64 and FP32+refinement solves; quality on the 2,007-node disk
   large3d  [0,1]^3 minus 64 random balls, h = 1/256 (about 16M nodes), n = 65,
            degree 4 (n + m = 100), with CSR
+  explicit explicit Euler steps of du/dt = lap u + 5 on the default node set
+           (faces u = x, sphere zero flux), each followed by the evaluation of
+           the four operators on the new field; weights computed beforehand
 
     python bench.py [--workload W] [--steps K] [--warmup W] [--no-cpu] ...
 
@@ -106,7 +109,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cube_sphere3d", choices=["cube_sphere3d", "mixed", "learned", "large3d"])
+    ap.add_argument("--workload", default="cube_sphere3d", choices=["cube_sphere3d", "mixed", "learned", "large3d", "explicit"])
     ap.add_argument("--form", default="f32_ir", choices=["f32_ir", "f64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="time only the reported form")
@@ -541,6 +544,120 @@ def bench_learned(a, torch, rb, B):
     return out
 
 
+# ---------------------------------------------------------------- explicit heat step
+def explicit_bytes(n_int, n_dir, n_neu, n, d, N):
+    """Algorithmic HBM bytes of one explicit step: per node its kind, row offset,
+    own value and result (the field is read once); interior rows the stencil
+    indices, Laplacian weights and source; Dirichlet rows g; Neumann rows the
+    indices, d gradient weight rows, the normal and g."""
+    return (N * (1 + 8 + 8 + 8) + n_int * (12.0 * n + 8) + n_dir * 8 +
+            n_neu * (4.0 * n + 8.0 * d * n + 8 * d + 8))
+
+
+def apply_bytes(N, n, R):
+    """Algorithmic HBM bytes of one application of R operators: row offsets,
+    indices, R weight rows, the field once and R outputs."""
+    return N * (8 + 4.0 * n + 8.0 * R * n + 8 + 8.0 * R)
+
+
+def bench_explicit(a, torch, rb, B):
+    import nodesets as ns
+    dev = torch.device("cuda:0")
+    wl = ns.workload("cube_sphere3d")
+    nd = wl["nodes"][0]
+    n, P, ops = wl["n"], wl["P"], wl["ops"]
+    N, d, R = nd.N, nd.d, len(wl["ops"])
+    c = np.array([0.5, 0.5, 0.5])
+    r = np.linalg.norm(nd.X - c, axis=1)
+    sphere = nd.is_boundary & (r < 0.3 + 1e-9)
+    kind = np.where(nd.is_boundary, rb.NODE_DIRICHLET, rb.NODE_INTERIOR).astype(np.uint8)
+    kind[sphere] = rb.NODE_NEUMANN
+    normals = np.zeros((N, 3))
+    normals[sphere] = (c - nd.X[sphere]) / r[sphere, None]
+    g = np.where(kind == rb.NODE_DIRICHLET, nd.X[:, 0], 0.0)
+    counts = [int((kind == k).sum()) for k in (rb.NODE_INTERIOR, rb.NODE_DIRICHLET, rb.NODE_NEUMANN)]
+    X = torch.from_numpy(nd.X).to(dev)
+    off_h = ns.offsets_from_sizes(np.full(N, n, dtype=np.int64))
+    off = torch.from_numpy(off_h).to(dev)
+    ctx = rb.context(dev)
+    idx = rb.select_stencils(X, off, n, ctx=ctx)
+    w, st = rb.compute_weights(X, off, idx, n, P, ops, precision="f64", ctx=ctx)
+    kt, nt, gt = (torch.from_numpy(v).to(dev) for v in (kind, normals, g))
+    s = torch.full((N,), 5.0, dtype=torch.float64, device=dev)
+    u = torch.where(kt == rb.NODE_DIRICHLET, gt, torch.zeros_like(gt))
+    v = torch.empty_like(u)
+    out = torch.empty((R, N), dtype=torch.float64, device=dev)
+    h = ns.CUBE_SPHERE_H
+    dt = 0.02 * h * h
+    timer = Timer(torch, ["explicit_step", "apply_operators"])
+    # the first step from u = 0 (the field stays bounded over the timed steps)
+    fields = [u, v]
+
+    def step(e):
+        if e:
+            e[0].record(timer.stream)
+        rb.explicit_step(off, idx, n, w[0], kt, fields[0], dt, w_grad=w[1:], normals=nt, g=gt, s=s, out=fields[1],
+                         ctx=ctx)
+        if e:
+            e[1].record(timer.stream)
+        rb.apply_operators(off, idx, w, n, fields[1], out=out, ctx=ctx)
+        if e:
+            e[2].record(timer.stream)
+        fields.reverse()
+
+    ms, wall, ph = timer.run(step, a.steps, a.warmup)
+    print(f"[bench] explicit: {ms:.4f} ms/step  phases {ph}", file=sys.stderr, flush=True)
+    eb = explicit_bytes(*counts, n, d, N)
+    ab = apply_bytes(N, n, R)
+    gbs_e = eb / (ph["explicit_step"] / 1e3) / 1e9
+    gbs_a = ab / (ph["apply_operators"] / 1e3) / 1e9
+    res = base_line(a, N / (ms / 1e3), ms, "f64",
+                    {"workload": "explicit_heat_cube_minus_sphere_3d", "N": N, "nnz": N * n, "n": n, "degree": P,
+                     "ops": list(ops), "interior_dirichlet_neumann": counts, "dt": dt,
+                     "step": "explicit_step (du/dt = lap u + 5; faces u = x, sphere zero flux) + "
+                             "apply_operators (lap, dx, dy, dz of the new field)"})
+    res["metric"] = "explicit Euler node updates/s (one step + evaluation of four operators)"
+    res["unit"] = "nodes/s"
+    res["roofline"] = {"bound": "hbm", "achieved": gbs_a, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                       "frac": gbs_a / PEAK_HBM_GBS, "traffic": None,
+                       "kernel": "k_apply<8,5,4>", "bytes_per_node": ab / N, "nodes_per_launch": N}
+    res["phases_roofline"] = {"explicit_step": {"bound": "hbm", "kernel": "k_explicit<8,5>", "bytes": eb,
+                                                "achieved_GBs": gbs_e, "frac": gbs_e / PEAK_HBM_GBS},
+                              "apply_operators": {"bound": "hbm", "kernel": "k_apply<8,5,4>", "bytes": ab,
+                                                  "achieved_GBs": gbs_a, "frac": gbs_a / PEAK_HBM_GBS}}
+    res["phases_ms"] = ph
+    res["wall_ms_per_step"] = wall
+    finite = bool(torch.isfinite(fields[0]).all().item())
+    res["field_finite"] = finite
+    if a.calib_copy:
+        calib_copy(torch, dev)
+    if not a.no_cpu:
+        res["cpu_baseline"] = cpu_explicit(nd, kind, normals, g, off_h, idx.cpu().numpy(), w.cpu().numpy(),
+                                           fields[0].cpu().numpy(), dt, N)
+    return res
+
+
+def cpu_explicit(nd, kind, normals, g, off, idx, W, u, dt, sample):
+    """The oracle's explicit step and operator application on the first `sample`
+    rows (about 5 us per row: the whole node set fits the time budget), one thread."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import explicit as oexp
+    S = min(sample, nd.N)
+    so, si = off[:S + 1], idx[:off[S]]
+    with threadpool_limits(limits=1):
+        t = time.perf_counter()
+        c0 = time.process_time()
+        oexp.explicit_step(so, si, W[0][:off[S]], W[1:, :off[S]], kind[:S], normals[:S], u, dt, g=g[:S],
+                           s=np.full(S, 5.0))
+        oexp.apply_operators(so, si, W[:, :off[S]], u)
+        dtw = time.perf_counter() - t
+        cpu_s = time.process_time() - c0
+    return {"value": S / dtw, "unit": "nodes/s", "cores": max(1, int(round(cpu_s / dtw))), "kind": "oracle",
+            "sample": f"{S} of {nd.N} nodes of the same workload (one explicit step + four operators), "
+                      f"{dtw:.1f} s wall, {cpu_s:.1f} s CPU, BLAS limited to one thread"}
+
+
 def main():
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -559,6 +676,8 @@ def main():
         out = bench_uniform(a, torch, rb, B, a.workload)
     elif a.workload == "mixed":
         out = bench_mixed(a, torch, rb, B)
+    elif a.workload == "explicit":
+        out = bench_explicit(a, torch, rb, B)
     else:
         out = bench_learned(a, torch, rb, B)
     print(json.dumps(out), flush=True)

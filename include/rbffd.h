@@ -7,7 +7,9 @@
  *   2. RBF-FD weights: for each stencil the augmented polyharmonic-spline plus
  *      monomial system of eq. (rbf-system-aug), solved for the Laplacian and
  *      first-derivative weights;
- *   3. the sparse operator in CSR form (at most sum n_i nonzeros).
+ *   3. the sparse operator in CSR form (at most sum n_i nonzeros);
+ *   4. explicit evaluation of the operators on a field and the explicit Euler
+ *      time step built from it (Sec. 2.3.1).
  *
  * Conventions shared by every call
  *   - All array arguments are DEVICE pointers unless stated otherwise.  The
@@ -196,6 +198,50 @@ rbf_status rbf_autotune_batched(rbf_ctx* ctx, const rbf_domain_desc* doms, int n
                                 const char* cache_path, rbf_plan* best);
 rbf_status rbf_set_plan(rbf_ctx* ctx, const rbf_plan* plan);   /* NULL: back to the default */
 rbf_status rbf_get_plan(const rbf_ctx* ctx, rbf_plan* plan);
+
+/* ------------------------------------------------------------------------ *
+ * Explicit evaluation (Sec. 2.3.1): an operator applied to a known field is
+ * the stencil dot product w_{L,p_i}^T u_{I(i)} at every node.
+ *
+ * out[r * N + i] = sum_{p = offsets[i]}^{offsets[i+1]-1} w[r * nnz + p] * u[idx[p]]
+ * for r < n_ops (1..4), float64.  u[n_u]; out[n_ops][N] may not alias u or w.
+ * n_max is the largest n_i and only chooses the lanes per row.  A row whose
+ * range lies outside [0, nnz] or holds an index outside [0, n_u) gets NaN; an
+ * empty row gets 0.  The summation order is fixed: results are reproducible
+ * run to run.  No workspace is needed.
+ * ------------------------------------------------------------------------ */
+rbf_status rbf_apply_operators(rbf_ctx* ctx, int64_t N, const int64_t* offsets,
+                               const int32_t* idx, const double* w, int n_ops, int64_t nnz,
+                               int n_max, const double* u, int64_t n_u, double* out);
+
+/* node kinds of the explicit step (uint8) */
+#define RBF_NODE_INTERIOR  0
+#define RBF_NODE_DIRICHLET 1
+#define RBF_NODE_NEUMANN   2
+
+/* ------------------------------------------------------------------------ *
+ * One explicit Euler step of du/dt = L u + s, eqs. (exp-start)-(exp-end):
+ *   interior node:  u_new[i] = u[i] + dt * (w_lap_i^T u_{I(i)} + s[i])
+ *   Dirichlet node: u_new[i] = g[i]                  (g NULL: u[i])
+ *   Neumann node:   with c_j = sum_l normal[i][l] * w_grad[l][offsets[i] + j],
+ *                   u_new[i] = (g[i] - sum_{j>=1} c_j u[idx[offsets[i]+j]]) / c_0
+ *                   (g NULL: zero flux), the discretised normal derivative of
+ *                   eq. (neu) equated to g and solved for u_i.
+ * kind[N] uint8 (RBF_NODE_*); w_lap[nnz]; w_grad: d rows of nnz values at
+ * w_grad + l * nnz (the DX..DZ rows of an rbf_compute_weights output), needed
+ * only when some node is Neumann; normals[N][d] (outward unit normals, read at
+ * Neumann nodes only); g[N] holds g_d((k+1) dt) at Dirichlet and g_n((k+1) dt)
+ * at Neumann nodes; s[N] the source (NULL: 0).  g and s may be NULL.
+ * Stencil position 0 must be node i itself (rbf_select_stencils puts it
+ * there).  A node with an invalid kind, row range or index, or a Neumann node
+ * whose first entry is not itself, gets NaN.  u_new may not alias u.
+ * d is 2 or 3.  No workspace is needed.
+ * ------------------------------------------------------------------------ */
+rbf_status rbf_explicit_step(rbf_ctx* ctx, int64_t N, int d, const int64_t* offsets,
+                             const int32_t* idx, int64_t nnz, int n_max,
+                             const double* w_lap, const double* w_grad, const uint8_t* kind,
+                             const double* normals, const double* g, const double* s,
+                             const double* u, double dt, double* u_new);
 
 /* ------------------------------------------------------------------------ *
  * Learned surrogate of the 2D, 15-node Laplacian weights (degree-2

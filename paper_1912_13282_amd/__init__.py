@@ -5,6 +5,8 @@ Python face of the HIP library ``librbffd.so`` (C ABI in include/rbffd.h):
     select_stencils  -- exact k-nearest-neighbour stencils, self first
     compute_weights  -- RBF-FD weights of the augmented PHS + monomial system
     assemble_csr     -- the sparse operator in CSR form
+    apply_operators  -- explicit evaluation w^T u_{I(i)} of the operators on a field
+    explicit_step    -- one explicit Euler step (interior, Dirichlet and Neumann nodes)
     compute_weights_batched / autotune_batched
                      -- mixed 2D/3D, per-node degree and size in one persistent launch
     mlp_* / surrogate_*
@@ -17,6 +19,7 @@ from ._binding import (  # noqa: F401
     OPS, ST_BADSIZE, ST_FALLBACK, ST_OK, ST_REFINED, ST_SINGULAR, ST_SURROGATE, ST_SURROGATE_REJECTED,
     Context, Domain, RbfError, assemble_csr, autotune_batched, compute_weights, compute_weights_batched, context,
     get_plan, lib, select_stencils, set_plan,
+    NODE_DIRICHLET, NODE_INTERIOR, NODE_NEUMANN, apply_operators, explicit_step,
     MLP_NPARAM, mlp_adam, mlp_flatten, mlp_forward, mlp_grad, mlp_pack, mlp_unflatten, surrogate_dataset,
     surrogate_load, surrogate_weights,
 )

@@ -79,6 +79,8 @@ _SIGS = {
     "rbf_surrogate_load": [_P, _P],
     "rbf_surrogate_weights": [_P, _P, _I64, _I, _P, _P, _I64, _I, ctypes.POINTER(rbf_options), _P, _P],
     "rbf_get_plan": [_P, ctypes.POINTER(rbf_plan)],
+    "rbf_apply_operators": [_P, _I64, _P, _P, _P, _I, _I64, _I, _P, _I64, _P],
+    "rbf_explicit_step": [_P, _I64, _I, _P, _P, _I64, _I, _P, _P, _P, _P, _P, _P, _P, ctypes.c_double, _P],
 }
 
 
@@ -238,6 +240,64 @@ def assemble_csr(offsets: torch.Tensor, idx: torch.Tensor, w: torch.Tensor | Non
                                   _dev(row_ptr, torch.int64, "row_ptr"), _dev(col, torch.int32, "col"), pv),
            "rbf_assemble_csr")
     return row_ptr, col, vals
+
+
+# ------------------------------------------------------------------ explicit evaluation
+NODE_INTERIOR, NODE_DIRICHLET, NODE_NEUMANN = 0, 1, 2
+
+
+def apply_operators(offsets: torch.Tensor, idx: torch.Tensor, w: torch.Tensor, n_max: int, u: torch.Tensor,
+                    out=None, ctx: Context | None = None) -> torch.Tensor:
+    """out [R, N] float64: out[r, i] = sum over stencil i of w[r, p] u[idx[p]] (w [R, nnz] or [nnz])."""
+    ctx = ctx or context(offsets.device)
+    N = offsets.numel() - 1
+    nnz = idx.numel()
+    w2 = w if w.dim() == 2 else w.reshape(1, -1)
+    R = w2.shape[0]
+    if w2.shape[1] != nnz:
+        raise RbfError(f"w has {w2.shape[1]} columns, idx {nnz} entries")
+    out = torch.empty((R, N), dtype=torch.float64, device=offsets.device) if out is None else out
+    if out.shape != (R, N):
+        raise RbfError(f"out must be [{R}, {N}], got {tuple(out.shape)}")
+    _check(lib().rbf_apply_operators(ctx._sync_stream(), N, _dev(offsets, torch.int64, "offsets"),
+                                     _dev(idx, torch.int32, "idx"), _dev(w2, torch.float64, "w"), R, nnz,
+                                     int(n_max), _dev(u, torch.float64, "u"), u.numel(),
+                                     _dev(out, torch.float64, "out")),
+           "rbf_apply_operators")
+    return out
+
+
+def explicit_step(offsets: torch.Tensor, idx: torch.Tensor, n_max: int, w_lap: torch.Tensor, kind: torch.Tensor,
+                  u: torch.Tensor, dt: float, w_grad=None, normals=None, g=None, s=None, out=None,
+                  ctx: Context | None = None) -> torch.Tensor:
+    """One explicit Euler step (kind uint8 [N]: NODE_INTERIOR / NODE_DIRICHLET / NODE_NEUMANN).
+
+    w_grad [d, nnz] and normals [N, d] serve the Neumann nodes; g [N] holds the
+    Dirichlet values and Neumann fluxes at the new time; s [N] the source."""
+    ctx = ctx or context(offsets.device)
+    N = offsets.numel() - 1
+    nnz = idx.numel()
+    d = normals.shape[1] if normals is not None else (w_grad.shape[0] if w_grad is not None else 2)
+    if w_lap.numel() != nnz or kind.numel() != N or u.numel() != N:
+        raise RbfError("w_lap must have nnz entries, kind and u N entries")
+    if w_grad is not None and tuple(w_grad.shape) != (d, nnz):
+        raise RbfError(f"w_grad must be [{d}, {nnz}], got {tuple(w_grad.shape)}")
+    if normals is not None and tuple(normals.shape) != (N, d):
+        raise RbfError(f"normals must be [{N}, {d}], got {tuple(normals.shape)}")
+    for name, t in (("g", g), ("s", s)):
+        if t is not None and t.numel() != N:
+            raise RbfError(f"{name} must have N entries")
+    out = torch.empty(N, dtype=torch.float64, device=offsets.device) if out is None else out
+    if out.numel() != N:
+        raise RbfError("out must have N entries")
+    opt = lambda t, name: None if t is None else _dev(t, torch.float64, name)  # noqa: E731
+    _check(lib().rbf_explicit_step(ctx._sync_stream(), N, d, _dev(offsets, torch.int64, "offsets"),
+                                   _dev(idx, torch.int32, "idx"), nnz, int(n_max), _dev(w_lap, torch.float64, "w_lap"),
+                                   opt(w_grad, "w_grad"), _dev(kind, torch.uint8, "kind"), opt(normals, "normals"),
+                                   opt(g, "g"), opt(s, "s"), _dev(u, torch.float64, "u"), float(dt),
+                                   _dev(out, torch.float64, "out")),
+           "rbf_explicit_step")
+    return out
 
 
 # ------------------------------------------------------------------ batched form

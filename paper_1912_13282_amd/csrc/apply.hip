@@ -1,0 +1,270 @@
+// Explicit evaluation of stencil operators on a field (Sec. 2.3.1): the dot
+// product of each node's weights with the field values at its stencil nodes,
+// and the explicit Euler step of eqs. (exp-start)-(exp-end) built from it.
+//
+// Both passes are bandwidth-bound: every stencil index and weight is read once
+// and the field is gathered (it stays in the caches when the node numbering is
+// spatially coherent).  One group of G lanes serves one row; a lane takes the
+// positions gl, gl + G, ..., and issues the E loads of a row segment before any
+// arithmetic so that they are in flight together.  The G partial sums are then
+// combined by a fixed butterfly, so the result does not depend on timing.
+#include "common.hpp"
+
+namespace {
+
+constexpr double kNaN = __builtin_nan("");
+
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+template <int G>
+__device__ __forceinline__ bool group_any(bool b) {
+    int v = b ? 1 : 0;
+#pragma unroll
+    for (int o = 1; o < G; o <<= 1) v |= __shfl_xor(v, o);
+    return v != 0;
+}
+
+// out[r][row] = sum_p w[r][p] u[idx[p]] over the row's range
+template <int G, int E, int R>
+__global__ __launch_bounds__(256) void k_apply(int64_t N, const int64_t* __restrict__ offsets,
+                                               const int32_t* __restrict__ idx, const double* __restrict__ w,
+                                               int64_t nnz, const double* __restrict__ u, int64_t n_u,
+                                               double* __restrict__ out) {
+    const int gl = threadIdx.x & (G - 1);
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    if (row >= N) return;  // whole groups leave together (G divides 64)
+    const int64_t off = offsets[row], end = offsets[row + 1];
+    bool bad = off < 0 || end < off || end > nnz;
+    const int64_t n = bad ? 0 : end - off;
+    double acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = 0.0;
+    for (int64_t base = 0; base < n; base += G * E) {
+        int j[E];
+        double wv[R][E], uv[E];
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            const int64_t e = base + gl + G * s;
+            j[s] = (e < n) ? idx[off + e] : 0;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int s = 0; s < E; ++s) {
+                const int64_t e = base + gl + G * s;
+                wv[r][s] = (e < n) ? w[r * nnz + off + e] : 0.0;
+            }
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            const int64_t e = base + gl + G * s;
+            const bool ok = j[s] >= 0 && (int64_t)j[s] < n_u;
+            bad |= (e < n) && !ok;
+            uv[s] = (e < n && ok) ? u[j[s]] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < E; ++s)
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r] = fma(wv[r][s], uv[s], acc[r]);
+    }
+    bad = group_any<G>(bad);
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = group_sum<G>(acc[r]);
+    if (gl < R) {
+        double v = acc[0];
+#pragma unroll
+        for (int r = 1; r < R; ++r)
+            if (gl == r) v = acc[r];
+        out[(int64_t)gl * N + row] = bad ? kNaN : v;
+    }
+}
+
+// One explicit Euler step: interior rows use the Laplacian weights, Neumann
+// rows the normal-derivative weights c_j = sum_l n_l w_grad[l][p] (Sec. 2.3.1).
+template <int G, int E>
+__global__ __launch_bounds__(256) void k_explicit(int64_t N, int d, const int64_t* __restrict__ offsets,
+                                                  const int32_t* __restrict__ idx, int64_t nnz,
+                                                  const double* __restrict__ w_lap, const double* __restrict__ w_grad,
+                                                  const uint8_t* __restrict__ kind, const double* __restrict__ normals,
+                                                  const double* __restrict__ g, const double* __restrict__ src,
+                                                  const double* __restrict__ u, double dt,
+                                                  double* __restrict__ u_new) {
+    const int gl = threadIdx.x & (G - 1);
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    if (row >= N) return;
+    const int k = kind[row];  // uniform over the group: every branch below is too
+    if (k == RBF_NODE_DIRICHLET) {
+        if (gl == 0) u_new[row] = g ? g[row] : u[row];
+        return;
+    }
+    if (k != RBF_NODE_INTERIOR && k != RBF_NODE_NEUMANN) {
+        if (gl == 0) u_new[row] = kNaN;
+        return;
+    }
+    const bool neu = k == RBF_NODE_NEUMANN;
+    if (neu && (!w_grad || !normals)) {
+        if (gl == 0) u_new[row] = kNaN;
+        return;
+    }
+    const int64_t off = offsets[row], end = offsets[row + 1];
+    bool bad = off < 0 || end < off || end > nnz || (neu && end == off);
+    const int64_t n = bad ? 0 : end - off;
+    double nrm[3] = {0.0, 0.0, 0.0};
+    if (neu)
+        for (int l = 0; l < d; ++l) nrm[l] = normals[row * d + l];
+    double acc = 0.0, c0 = 0.0;
+    for (int64_t base = 0; base < n; base += G * E) {
+        int j[E];
+        double wv[E], uv[E];
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            const int64_t e = base + gl + G * s;
+            j[s] = (e < n) ? idx[off + e] : 0;
+        }
+        if (!neu) {
+#pragma unroll
+            for (int s = 0; s < E; ++s) {
+                const int64_t e = base + gl + G * s;
+                wv[s] = (e < n) ? w_lap[off + e] : 0.0;
+            }
+        } else {
+#pragma unroll
+            for (int s = 0; s < E; ++s) {
+                const int64_t e = base + gl + G * s;
+                double c = 0.0;
+                if (e < n)
+                    for (int l = 0; l < d; ++l) c = fma(nrm[l], w_grad[l * nnz + off + e], c);
+                wv[s] = c;
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            const int64_t e = base + gl + G * s;
+            const bool ok = j[s] >= 0 && (int64_t)j[s] < N;
+            bad |= (e < n) && !ok;
+            uv[s] = (e < n && ok) ? u[j[s]] : 0.0;
+        }
+#pragma unroll
+        for (int s = 0; s < E; ++s) {
+            const int64_t e = base + gl + G * s;
+            if (neu && e == 0) {
+                c0 = wv[s];                   // the node's own coefficient
+                bad |= j[s] != (int32_t)row;  // position 0 must be the node itself
+            } else {
+                acc = fma(wv[s], uv[s], acc);
+            }
+        }
+    }
+    bad = group_any<G>(bad);
+    acc = group_sum<G>(acc);
+    if (neu) c0 = group_sum<G>(c0);
+    if (gl == 0) {
+        double v;
+        if (neu)
+            v = ((g ? g[row] : 0.0) - acc) / c0;
+        else
+            v = u[row] + dt * (acc + (src ? src[row] : 0.0));
+        u_new[row] = bad ? kNaN : v;
+    }
+}
+
+// Lanes per row and positions per lane for the largest row: G = 8 up to 64
+// positions (E = ceil(n_max / 8)), then 16 x 8, then 64 lanes looping by 4.
+template <template <int, int> class L, typename... A>
+hipError_t dispatch_shape(int n_max, int64_t N, hipStream_t s, A... args) {
+    auto go = [&](auto gt, auto et) {
+        constexpr int G = decltype(gt)::value, E = decltype(et)::value;
+        const int64_t threads = N * G;
+        return L<G, E>::launch(dim3((unsigned)((threads + 255) / 256)), s, args...);
+    };
+    using std::integral_constant;
+    switch (n_max <= 64 ? (n_max + 7) / 8 : 0) {
+        case 1: return go(integral_constant<int, 8>(), integral_constant<int, 1>());
+        case 2: return go(integral_constant<int, 8>(), integral_constant<int, 2>());
+        case 3: return go(integral_constant<int, 8>(), integral_constant<int, 3>());
+        case 4: return go(integral_constant<int, 8>(), integral_constant<int, 4>());
+        case 5: return go(integral_constant<int, 8>(), integral_constant<int, 5>());
+        case 6: return go(integral_constant<int, 8>(), integral_constant<int, 6>());
+        case 7: return go(integral_constant<int, 8>(), integral_constant<int, 7>());
+        case 8: return go(integral_constant<int, 8>(), integral_constant<int, 8>());
+        default: break;
+    }
+    if (n_max <= 128) return go(integral_constant<int, 16>(), integral_constant<int, 8>());
+    return go(integral_constant<int, 64>(), integral_constant<int, 4>());
+}
+
+template <int R>
+struct ApplyL {
+    template <int G, int E>
+    struct L {
+        static hipError_t launch(dim3 grid, hipStream_t s, int64_t N, const int64_t* offsets, const int32_t* idx,
+                                 const double* w, int64_t nnz, const double* u, int64_t n_u, double* out) {
+            hipLaunchKernelGGL((k_apply<G, E, R>), grid, dim3(256), 0, s, N, offsets, idx, w, nnz, u, n_u, out);
+            return hipGetLastError();
+        }
+    };
+};
+
+template <int G, int E>
+struct ExplicitL {
+    static hipError_t launch(dim3 grid, hipStream_t s, int64_t N, int d, const int64_t* offsets, const int32_t* idx,
+                             int64_t nnz, const double* w_lap, const double* w_grad, const uint8_t* kind,
+                             const double* normals, const double* g, const double* src, const double* u, double dt,
+                             double* u_new) {
+        hipLaunchKernelGGL((k_explicit<G, E>), grid, dim3(256), 0, s, N, d, offsets, idx, nnz, w_lap, w_grad, kind,
+                           normals, g, src, u, dt, u_new);
+        return hipGetLastError();
+    }
+};
+
+// true if [a, a + na) and [b, b + nb) (bytes) overlap
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+}  // namespace
+
+extern "C" rbf_status rbf_apply_operators(rbf_ctx* ctx, int64_t N, const int64_t* offsets, const int32_t* idx,
+                                          const double* w, int n_ops, int64_t nnz, int n_max, const double* u,
+                                          int64_t n_u, double* out) {
+    if (!ctx || !offsets || !w || !u || !out || N < 1 || nnz < 0 || n_max < 1 || n_u < 1) return RBF_EINVAL;
+    if (nnz > 0 && !idx) return RBF_EINVAL;
+    if (n_ops < 1 || n_ops > 4) return RBF_EINVAL;
+    if (n_u > INT32_MAX + (int64_t)1) return RBF_EINVAL;  // indices are int32
+    const size_t out_b = (size_t)n_ops * (size_t)N * sizeof(double);
+    if (overlap(out, out_b, u, (size_t)n_u * sizeof(double)) ||
+        overlap(out, out_b, w, (size_t)n_ops * (size_t)nnz * sizeof(double)))
+        return RBF_EINVAL;
+    RBF_HIP_CHECK(hipSetDevice(ctx->device));
+    hipError_t e;
+    switch (n_ops) {
+        case 1: e = dispatch_shape<ApplyL<1>::L>(n_max, N, ctx->stream, N, offsets, idx, w, nnz, u, n_u, out); break;
+        case 2: e = dispatch_shape<ApplyL<2>::L>(n_max, N, ctx->stream, N, offsets, idx, w, nnz, u, n_u, out); break;
+        case 3: e = dispatch_shape<ApplyL<3>::L>(n_max, N, ctx->stream, N, offsets, idx, w, nnz, u, n_u, out); break;
+        default: e = dispatch_shape<ApplyL<4>::L>(n_max, N, ctx->stream, N, offsets, idx, w, nnz, u, n_u, out); break;
+    }
+    return e == hipSuccess ? RBF_OK : RBF_EHIP;
+}
+
+extern "C" rbf_status rbf_explicit_step(rbf_ctx* ctx, int64_t N, int d, const int64_t* offsets, const int32_t* idx,
+                                        int64_t nnz, int n_max, const double* w_lap, const double* w_grad,
+                                        const uint8_t* kind, const double* normals, const double* g, const double* s,
+                                        const double* u, double dt, double* u_new) {
+    if (!ctx || !offsets || !w_lap || !kind || !u || !u_new || N < 1 || nnz < 0 || n_max < 1) return RBF_EINVAL;
+    if (nnz > 0 && !idx) return RBF_EINVAL;
+    if (d != 2 && d != 3) return RBF_EDIM;
+    if (N > INT32_MAX + (int64_t)1) return RBF_EINVAL;
+    // Neumann rows need w_grad and normals; given neither, every Neumann row gets NaN
+    if ((w_grad == nullptr) != (normals == nullptr)) return RBF_EINVAL;
+    const size_t nb = (size_t)N * sizeof(double);
+    if (overlap(u_new, nb, u, nb) || overlap(u_new, nb, w_lap, (size_t)nnz * sizeof(double))) return RBF_EINVAL;
+    RBF_HIP_CHECK(hipSetDevice(ctx->device));
+    const hipError_t e = dispatch_shape<ExplicitL>(n_max, N, ctx->stream, N, d, offsets, idx, nnz, w_lap, w_grad,
+                                                   kind, normals, g, s, u, dt, u_new);
+    return e == hipSuccess ? RBF_OK : RBF_EHIP;
+}
