@@ -17,6 +17,11 @@ Other workloads (the same JSON contract, one line each):
            plain FP64 and FP32+refinement solves; quality on the 2,007-node disk
   large3d  [0,1]^3 minus 64 random balls, h = 1/256 (about 16M nodes), n = 65,
            degree 4 (n + m = 100), with CSR
+  poisson3d / poisson2d
+           the benchmark problem of Sec. 5: -lap u = f on the annulus B(0,1)
+           minus B(0,1/2), u_0 = prod sin(pi x_a) on the boundary, n = 35 (3D) or
+           9 (2D), degree 2, about 1M nodes; stencils, weights, implicit
+           assembly and BiCGStab (Jacobi scaling, tol 1e-10) per step
   explicit explicit Euler steps of du/dt = lap u + 5 on the default node set
            (faces u = x, sphere zero flux), each followed by the evaluation of
            the four operators on the new field; weights computed beforehand
@@ -109,7 +114,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cube_sphere3d", choices=["cube_sphere3d", "mixed", "learned", "large3d", "explicit"])
+    ap.add_argument("--workload", default="cube_sphere3d", choices=["cube_sphere3d", "mixed", "learned", "large3d", "explicit", "poisson3d", "poisson2d"])
     ap.add_argument("--form", default="f32_ir", choices=["f32_ir", "f64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="time only the reported form")
@@ -658,6 +663,128 @@ def cpu_explicit(nd, kind, normals, g, off, idx, W, u, dt, sample):
                       f"{dtw:.1f} s wall, {cpu_s:.1f} s CPU, BLAS limited to one thread"}
 
 
+# ---------------------------------------------------------------- implicit Poisson (Sec. 5)
+POISSON_CASES = {
+    # name: (d, n, degree, h) -- the annulus B(0,1) minus B(0,1/2); about 1M nodes each
+    "poisson3d": (3, 35, 2, 0.0154),
+    "poisson2d": (2, 9, 2, 0.00154),
+}
+
+
+def bicgstab_bytes_per_row(n):
+    """Algorithmic HBM bytes per row of one BiCGStab iteration: two row products
+    (row offset, n indices and values, the gathered vector once, the inverse
+    diagonal, one dot operand, the result) and the three vector passes
+    (p: 3 reads + 1 write, s: 2 + 1, x and r: 5 + 2)."""
+    return 2 * (8 + 12.0 * n + 8 + 8 + 8 + 8) + 8 * (4 + 3 + 7)
+
+
+def bench_poisson(a, torch, rb, B):
+    import nodesets as ns
+    from oracle import poisson as opoi
+    dev = torch.device("cuda:0")
+    d, n, P, h = POISSON_CASES[a.workload]
+    t = time.perf_counter()
+    nd = ns.annulus(h, 1006, d=d)
+    N = nd.N
+    print(f"[bench] {a.workload}: {N} nodes generated in {time.perf_counter() - t:.1f} s", file=sys.stderr, flush=True)
+    X = torch.from_numpy(nd.X).to(dev)
+    off = torch.from_numpy(ns.offsets_from_sizes(np.full(N, n, dtype=np.int64))).to(dev)
+    nnz = N * n
+    ctx = rb.context(dev)
+    idx = torch.empty(nnz, dtype=torch.int32, device=dev)
+    ws = torch.empty(B.select_stencils_workspace(N, d, n), dtype=torch.uint8, device=dev)
+    w = torch.empty((1, nnz), dtype=torch.float64, device=dev)
+    status = torch.empty(N, dtype=torch.int8, device=dev)
+    kind = torch.from_numpy(np.where(nd.is_boundary, rb.NODE_DIRICHLET, rb.NODE_INTERIOR).astype(np.uint8)).to(dev)
+    u0 = opoi.u0(nd.X)
+    f = torch.from_numpy(opoi.lap_u0(nd.X)).to(dev)
+    g = torch.from_numpy(u0).to(dev)
+    vals = torch.empty(nnz, dtype=torch.float64, device=dev)
+    rhs = torch.empty(N, dtype=torch.float64, device=dev)
+    x = torch.empty(N, dtype=torch.float64, device=dev)
+    sws = torch.empty(rb.bicgstab_workspace(N), dtype=torch.uint8, device=dev)
+    tol = 1e-10
+    timer = Timer(torch, ["select_stencils", "compute_weights", "assemble_implicit", "bicgstab"])
+    infos = []
+
+    def step(e):
+        if e:
+            e[0].record(timer.stream)
+        rb.select_stencils(X, off, n, idx=idx, workspace=ws, ctx=ctx)
+        if e:
+            e[1].record(timer.stream)
+        rb.compute_weights(X, off, idx, n, P, ("lap",), precision="f64", w=w, status=status, ctx=ctx)
+        if e:
+            e[2].record(timer.stream)
+        rb.assemble_implicit(off, idx, w[0], kind, f=f, g=g, d=d, vals=vals, rhs=rhs, ctx=ctx)
+        if e:
+            e[3].record(timer.stream)
+        x.zero_()
+        _, info = rb.bicgstab(off, idx, vals, n, rhs, x=x, tol=tol, max_iter=100000, precond="jacobi",
+                              workspace=sws, ctx=ctx)
+        if e:
+            e[4].record(timer.stream)
+        infos.append(info)
+
+    ms, wall, ph = timer.run(step, a.steps, a.warmup)
+    info = infos[-1]
+    err = float(np.abs(x.cpu().numpy() - u0).max())
+    print(f"[bench] {a.workload}: {ms:.2f} ms/step  phases {ph}  solve {info}  max error {err:.3e}",
+          file=sys.stderr, flush=True)
+    it = max(1, info["iterations"])
+    per_it = bicgstab_bytes_per_row(n) * N
+    gbs = per_it * it / (ph["bicgstab"] / 1e3) / 1e9
+    res = base_line(a, N / (ms / 1e3), ms, "f64",
+                    {"workload": f"poisson_annulus_{d}d", "N": N, "nnz": nnz, "n": n, "degree": P, "ops": ["lap"],
+                     "solver": "BiCGStab, Jacobi row scaling", "tol": tol,
+                     "step": "select_stencils + compute_weights + assemble_implicit + bicgstab"})
+    res["metric"] = "Poisson nodes solved/s (stencils + weights + assembly + BiCGStab)"
+    res["unit"] = "nodes/s"
+    res["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                       "frac": gbs / PEAK_HBM_GBS, "traffic": None,
+                       "kernel": f"BiCGStab iteration (k_vec<P>, k_spmv<8,{(n + 7) // 8},V>, k_vec<S>, "
+                                 f"k_spmv<8,{(n + 7) // 8},T>, k_vec<X>)",
+                       "bytes_per_row_per_iteration": bicgstab_bytes_per_row(n), "rows": N, "iterations": it}
+    res["phases_ms"] = ph
+    res["wall_ms_per_step"] = wall
+    res["solve"] = info
+    res["max_error_vs_u0"] = err
+    if a.calib_copy:
+        calib_copy(torch, dev)
+    if not a.no_cpu:
+        res["cpu_baseline"] = cpu_poisson(d, n, P)
+    return res
+
+
+def cpu_poisson(d, n, P):
+    """The oracle pipeline (exact kNN, weights by LAPACK per stencil, assembly,
+    sparse direct solve) on a smaller annulus of the same kind, one BLAS thread."""
+    from threadpoolctl import threadpool_limits
+
+    import nodesets as ns
+    from oracle import implicit as oimp
+    from oracle import knn as oknn
+    from oracle import poisson as opoi
+    from oracle import rbffd as orbf
+    h = 0.06 if d == 3 else 0.012
+    nd = ns.annulus(h, 1006, d=d)
+    N = nd.N
+    with threadpool_limits(limits=1):
+        t = time.perf_counter()
+        c0 = time.process_time()
+        off, idx = oknn.knn_exact(nd.X, n)
+        W, _ = orbf.weights(nd.X, off, idx, P, ("lap",))
+        kind = np.where(nd.is_boundary, oimp.DIRICHLET, oimp.INTERIOR)
+        vals, rhs = oimp.assemble(off, idx, W[0], None, kind, None, f=opoi.lap_u0(nd.X), g=opoi.u0(nd.X))
+        oimp.solve(off, idx, vals, rhs)
+        dt = time.perf_counter() - t
+        cpu_s = time.process_time() - c0
+    return {"value": N / dt, "unit": "nodes/s", "cores": max(1, int(round(cpu_s / dt))), "kind": "oracle",
+            "sample": f"the same problem on a coarser annulus (h = {h}, {N} nodes): kNN + weights + assembly + "
+                      f"sparse direct solve, {dt:.1f} s wall, {cpu_s:.1f} s CPU, BLAS limited to one thread"}
+
+
 def main():
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -678,6 +805,8 @@ def main():
         out = bench_mixed(a, torch, rb, B)
     elif a.workload == "explicit":
         out = bench_explicit(a, torch, rb, B)
+    elif a.workload in POISSON_CASES:
+        out = bench_poisson(a, torch, rb, B)
     else:
         out = bench_learned(a, torch, rb, B)
     print(json.dumps(out), flush=True)

@@ -9,7 +9,9 @@
  *      first-derivative weights;
  *   3. the sparse operator in CSR form (at most sum n_i nonzeros);
  *   4. explicit evaluation of the operators on a field and the explicit Euler
- *      time step built from it (Sec. 2.3.1).
+ *      time step built from it (Sec. 2.3.1);
+ *   5. the implicit system M u = r of a boundary value problem and its
+ *      iterative solution on the GPU (Sec. 2.3.2, Sec. 5).
  *
  * Conventions shared by every call
  *   - All array arguments are DEVICE pointers unless stated otherwise.  The
@@ -242,6 +244,63 @@ rbf_status rbf_explicit_step(rbf_ctx* ctx, int64_t N, int d, const int64_t* offs
                              const double* w_lap, const double* w_grad, const uint8_t* kind,
                              const double* normals, const double* g, const double* s,
                              const double* u, double dt, double* u_new);
+
+/* ------------------------------------------------------------------------ *
+ * Implicit system, eqs. (implicit-start)-(implicit-end) of Sec. 2.3.2, for
+ * L u = f in the domain, u = g_d on Dirichlet and du/dn = g_n on Neumann nodes:
+ *   interior row i:  M[i][idx[p]] = w_lap[p],                     r[i] = f[i]
+ *   Dirichlet row i: M[i][i] = 1,                                  r[i] = g[i]
+ *   Neumann row i:   M[i][idx[p]] = sum_l normals[i][l] w_grad[l][p], r[i] = g[i]
+ * for p in the row's range.  M is written in the stencil layout (the same
+ * offsets and idx; vals[nnz] float64): a Dirichlet row keeps its n_i slots,
+ * 1 at position 0 (the node itself) and explicit zeros elsewhere.
+ * rbf_assemble_csr turns it into CSR with ascending columns.  kind, w_grad,
+ * normals as for rbf_explicit_step; f and g may be NULL (zero).  A row with an
+ * invalid kind or range, or a Dirichlet / Neumann row whose position 0 is not
+ * the node itself, gets NaN in r (and in its vals where the range is valid).
+ * No workspace is needed.
+ * ------------------------------------------------------------------------ */
+rbf_status rbf_assemble_implicit(rbf_ctx* ctx, int64_t N, int d, const int64_t* offsets,
+                                 const int32_t* idx, int64_t nnz, const double* w_lap,
+                                 const double* w_grad, const uint8_t* kind, const double* normals,
+                                 const double* f, const double* g, double* vals, double* rhs);
+
+/* iterative solver preconditioners and outcomes */
+#define RBF_PRECOND_NONE    0
+#define RBF_PRECOND_JACOBI  1   /* rows scaled by the inverse diagonal */
+
+#define RBF_SOLVE_CONVERGED  0
+#define RBF_SOLVE_MAXITER    1
+#define RBF_SOLVE_BREAKDOWN  2  /* a BiCGStab denominator vanished or a value is not finite */
+#define RBF_SOLVE_BADDIAG    3  /* Jacobi: a row without a finite nonzero diagonal entry */
+
+typedef struct rbf_solve_info {
+    int32_t status;          /* RBF_SOLVE_*                                               */
+    int32_t iterations;      /* BiCGStab iterations taken                                 */
+    double  residual;        /* ||D^-1 (r - M x)|| / ||D^-1 r||, the monitored residual   */
+    double  true_residual;   /* ||r - M x|| / ||r|| of the returned x, recomputed         */
+} rbf_solve_info;
+
+/* ------------------------------------------------------------------------ *
+ * Solution of M x = r (Sec. 2.3.2) by BiCGStab (van der Vorst 1992), the
+ * Krylov method the paper's benchmark uses (Sec. 5), in float64 on the GPU.
+ *
+ * M: N rows in the stencil layout or CSR (row_ptr = offsets, col = idx, vals
+ * [nnz]); n_max bounds the row lengths.  x[N]: initial guess in, solution out.
+ * Preconditioner: RBF_PRECOND_JACOBI solves D^-1 M x = D^-1 r with D the
+ * diagonal of M (the first entry of row i in column i), RBF_PRECOND_NONE with
+ * D = I.  Stops when ||D^-1 (r - M x)|| <= tol ||D^-1 r|| or after max_iter
+ * iterations.  Every step runs on the device (no host round trip inside an
+ * iteration); the call waits for the context stream every 16 iterations and
+ * on return, when *info (host memory, may be NULL) is filled.  Deterministic:
+ * every dot product is reduced in a fixed order.  Workspace:
+ * rbf_bicgstab_workspace (7 N + 8192 float64 values).
+ * ------------------------------------------------------------------------ */
+rbf_status rbf_bicgstab_workspace(int64_t N, size_t* bytes);
+rbf_status rbf_bicgstab(rbf_ctx* ctx, int64_t N, const int64_t* offsets, const int32_t* idx,
+                        const double* vals, int64_t nnz, int n_max, const double* rhs, double* x,
+                        double tol, int max_iter, int precond, void* workspace, size_t ws_bytes,
+                        rbf_solve_info* info);
 
 /* ------------------------------------------------------------------------ *
  * Learned surrogate of the 2D, 15-node Laplacian weights (degree-2

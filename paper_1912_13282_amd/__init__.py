@@ -7,6 +7,8 @@ Python face of the HIP library ``librbffd.so`` (C ABI in include/rbffd.h):
     assemble_csr     -- the sparse operator in CSR form
     apply_operators  -- explicit evaluation w^T u_{I(i)} of the operators on a field
     explicit_step    -- one explicit Euler step (interior, Dirichlet and Neumann nodes)
+    assemble_implicit / bicgstab
+                     -- the implicit system M u = r and its BiCGStab solution on the GPU
     compute_weights_batched / autotune_batched
                      -- mixed 2D/3D, per-node degree and size in one persistent launch
     mlp_* / surrogate_*
@@ -20,6 +22,7 @@ from ._binding import (  # noqa: F401
     Context, Domain, RbfError, assemble_csr, autotune_batched, compute_weights, compute_weights_batched, context,
     get_plan, lib, select_stencils, set_plan,
     NODE_DIRICHLET, NODE_INTERIOR, NODE_NEUMANN, apply_operators, explicit_step,
+    SOLVE_BADDIAG, SOLVE_BREAKDOWN, SOLVE_CONVERGED, SOLVE_MAXITER, assemble_implicit, bicgstab, bicgstab_workspace,
     MLP_NPARAM, mlp_adam, mlp_flatten, mlp_forward, mlp_grad, mlp_pack, mlp_unflatten, surrogate_dataset,
     surrogate_load, surrogate_weights,
 )

@@ -45,6 +45,11 @@ class rbf_domain_desc(ctypes.Structure):
                 ("w", ctypes.c_void_p), ("status", ctypes.c_void_p)]
 
 
+class rbf_solve_info(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("iterations", ctypes.c_int32), ("residual", ctypes.c_double),
+                ("true_residual", ctypes.c_double)]
+
+
 class rbf_plan(ctypes.Structure):
     _fields_ = [("chunk", ctypes.c_int), ("waves_per_cu", ctypes.c_int), ("ms", ctypes.c_float)]
 
@@ -81,6 +86,10 @@ _SIGS = {
     "rbf_get_plan": [_P, ctypes.POINTER(rbf_plan)],
     "rbf_apply_operators": [_P, _I64, _P, _P, _P, _I, _I64, _I, _P, _I64, _P],
     "rbf_explicit_step": [_P, _I64, _I, _P, _P, _I64, _I, _P, _P, _P, _P, _P, _P, _P, ctypes.c_double, _P],
+    "rbf_assemble_implicit": [_P, _I64, _I, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P],
+    "rbf_bicgstab_workspace": [_I64, ctypes.POINTER(_SZ)],
+    "rbf_bicgstab": [_P, _I64, _P, _P, _P, _I64, _I, _P, _P, ctypes.c_double, _I, _I, _P, _SZ,
+                     ctypes.POINTER(rbf_solve_info)],
 }
 
 
@@ -298,6 +307,77 @@ def explicit_step(offsets: torch.Tensor, idx: torch.Tensor, n_max: int, w_lap: t
                                    _dev(out, torch.float64, "out")),
            "rbf_explicit_step")
     return out
+
+
+# ------------------------------------------------------------------ implicit solution
+SOLVE_CONVERGED, SOLVE_MAXITER, SOLVE_BREAKDOWN, SOLVE_BADDIAG = 0, 1, 2, 3
+PRECOND = {"none": 0, "jacobi": 1}
+
+
+def assemble_implicit(offsets: torch.Tensor, idx: torch.Tensor, w_lap: torch.Tensor, kind: torch.Tensor,
+                      w_grad=None, normals=None, f=None, g=None, d: int | None = None, vals=None, rhs=None,
+                      ctx: Context | None = None):
+    """(vals [nnz], rhs [N]) of the implicit system M u = r in the stencil layout."""
+    ctx = ctx or context(offsets.device)
+    N = offsets.numel() - 1
+    nnz = idx.numel()
+    if d is None:
+        d = normals.shape[1] if normals is not None else (w_grad.shape[0] if w_grad is not None else 2)
+    if w_lap.numel() != nnz or kind.numel() != N:
+        raise RbfError("w_lap must have nnz entries and kind N entries")
+    if w_grad is not None and tuple(w_grad.shape) != (d, nnz):
+        raise RbfError(f"w_grad must be [{d}, {nnz}]")
+    if normals is not None and tuple(normals.shape) != (N, d):
+        raise RbfError(f"normals must be [{N}, {d}]")
+    for name, t in (("f", f), ("g", g)):
+        if t is not None and t.numel() != N:
+            raise RbfError(f"{name} must have N entries")
+    dev = offsets.device
+    vals = torch.empty(nnz, dtype=torch.float64, device=dev) if vals is None else vals
+    rhs = torch.empty(N, dtype=torch.float64, device=dev) if rhs is None else rhs
+    opt = lambda t, name: None if t is None else _dev(t, torch.float64, name)  # noqa: E731
+    _check(lib().rbf_assemble_implicit(ctx._sync_stream(), N, int(d), _dev(offsets, torch.int64, "offsets"),
+                                       _dev(idx, torch.int32, "idx"), nnz, _dev(w_lap, torch.float64, "w_lap"),
+                                       opt(w_grad, "w_grad"), _dev(kind, torch.uint8, "kind"), opt(normals, "normals"),
+                                       opt(f, "f"), opt(g, "g"), _dev(vals, torch.float64, "vals"),
+                                       _dev(rhs, torch.float64, "rhs")),
+           "rbf_assemble_implicit")
+    return vals, rhs
+
+
+def bicgstab_workspace(N: int) -> int:
+    b = ctypes.c_size_t()
+    _check(lib().rbf_bicgstab_workspace(N, ctypes.byref(b)), "rbf_bicgstab_workspace")
+    return b.value
+
+
+def bicgstab(offsets: torch.Tensor, idx: torch.Tensor, vals: torch.Tensor, n_max: int, rhs: torch.Tensor,
+             x: torch.Tensor | None = None, tol: float = 1e-10, max_iter: int = 10000, precond: str = "jacobi",
+             workspace: torch.Tensor | None = None, ctx: Context | None = None):
+    """Solve M x = rhs by BiCGStab on the GPU; returns (x, info dict).  x (if given) is the
+    initial guess and is overwritten; otherwise the solve starts from zero."""
+    ctx = ctx or context(offsets.device)
+    N = offsets.numel() - 1
+    nnz = idx.numel()
+    if vals.numel() != nnz or rhs.numel() != N:
+        raise RbfError("vals must have nnz entries and rhs N entries")
+    if precond not in PRECOND:
+        raise RbfError(f"precond must be one of {sorted(PRECOND)}")
+    x = torch.zeros(N, dtype=torch.float64, device=offsets.device) if x is None else x
+    if x.numel() != N:
+        raise RbfError("x must have N entries")
+    ws_bytes = bicgstab_workspace(N)
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=offsets.device)
+    info = rbf_solve_info()
+    _check(lib().rbf_bicgstab(ctx._sync_stream(), N, _dev(offsets, torch.int64, "offsets"),
+                              _dev(idx, torch.int32, "idx"), _dev(vals, torch.float64, "vals"), nnz, int(n_max),
+                              _dev(rhs, torch.float64, "rhs"), _dev(x, torch.float64, "x"), float(tol),
+                              int(max_iter), PRECOND[precond], _dev(workspace, torch.uint8, "workspace"),
+                              workspace.numel(), ctypes.byref(info)),
+           "rbf_bicgstab")
+    return x, {"status": info.status, "iterations": info.iterations, "residual": info.residual,
+               "true_residual": info.true_residual}
 
 
 # ------------------------------------------------------------------ batched form

@@ -4,30 +4,12 @@
 //
 // Both passes are bandwidth-bound: every stencil index and weight is read once
 // and the field is gathered (it stays in the caches when the node numbering is
-// spatially coherent).  One group of G lanes serves one row; a lane takes the
-// positions gl, gl + G, ..., and issues the E loads of a row segment before any
-// arithmetic so that they are in flight together.  The G partial sums are then
-// combined by a fixed butterfly, so the result does not depend on timing.
-#include "common.hpp"
+// spatially coherent).  Rows are served by groups of lanes (rowdot.hpp).
+#include "rowdot.hpp"
+
+using namespace rbf;
 
 namespace {
-
-constexpr double kNaN = __builtin_nan("");
-
-template <int G>
-__device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-    for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o);
-    return v;
-}
-
-template <int G>
-__device__ __forceinline__ bool group_any(bool b) {
-    int v = b ? 1 : 0;
-#pragma unroll
-    for (int o = 1; o < G; o <<= 1) v |= __shfl_xor(v, o);
-    return v != 0;
-}
 
 // out[r][row] = sum_p w[r][p] u[idx[p]] over the row's range
 template <int G, int E, int R>
@@ -44,33 +26,7 @@ __global__ __launch_bounds__(256) void k_apply(int64_t N, const int64_t* __restr
     double acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = 0.0;
-    for (int64_t base = 0; base < n; base += G * E) {
-        int j[E];
-        double wv[R][E], uv[E];
-#pragma unroll
-        for (int s = 0; s < E; ++s) {
-            const int64_t e = base + gl + G * s;
-            j[s] = (e < n) ? idx[off + e] : 0;
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r)
-#pragma unroll
-            for (int s = 0; s < E; ++s) {
-                const int64_t e = base + gl + G * s;
-                wv[r][s] = (e < n) ? w[r * nnz + off + e] : 0.0;
-            }
-#pragma unroll
-        for (int s = 0; s < E; ++s) {
-            const int64_t e = base + gl + G * s;
-            const bool ok = j[s] >= 0 && (int64_t)j[s] < n_u;
-            bad |= (e < n) && !ok;
-            uv[s] = (e < n && ok) ? u[j[s]] : 0.0;
-        }
-#pragma unroll
-        for (int s = 0; s < E; ++s)
-#pragma unroll
-            for (int r = 0; r < R; ++r) acc[r] = fma(wv[r][s], uv[s], acc[r]);
-    }
+    row_dot_partial<G, E, R>(idx, w, nnz, off, n, u, n_u, gl, acc, bad);
     bad = group_any<G>(bad);
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = group_sum<G>(acc[r]);
@@ -172,31 +128,6 @@ __global__ __launch_bounds__(256) void k_explicit(int64_t N, int d, const int64_
     }
 }
 
-// Lanes per row and positions per lane for the largest row: G = 8 up to 64
-// positions (E = ceil(n_max / 8)), then 16 x 8, then 64 lanes looping by 4.
-template <template <int, int> class L, typename... A>
-hipError_t dispatch_shape(int n_max, int64_t N, hipStream_t s, A... args) {
-    auto go = [&](auto gt, auto et) {
-        constexpr int G = decltype(gt)::value, E = decltype(et)::value;
-        const int64_t threads = N * G;
-        return L<G, E>::launch(dim3((unsigned)((threads + 255) / 256)), s, args...);
-    };
-    using std::integral_constant;
-    switch (n_max <= 64 ? (n_max + 7) / 8 : 0) {
-        case 1: return go(integral_constant<int, 8>(), integral_constant<int, 1>());
-        case 2: return go(integral_constant<int, 8>(), integral_constant<int, 2>());
-        case 3: return go(integral_constant<int, 8>(), integral_constant<int, 3>());
-        case 4: return go(integral_constant<int, 8>(), integral_constant<int, 4>());
-        case 5: return go(integral_constant<int, 8>(), integral_constant<int, 5>());
-        case 6: return go(integral_constant<int, 8>(), integral_constant<int, 6>());
-        case 7: return go(integral_constant<int, 8>(), integral_constant<int, 7>());
-        case 8: return go(integral_constant<int, 8>(), integral_constant<int, 8>());
-        default: break;
-    }
-    if (n_max <= 128) return go(integral_constant<int, 16>(), integral_constant<int, 8>());
-    return go(integral_constant<int, 64>(), integral_constant<int, 4>());
-}
-
 template <int R>
 struct ApplyL {
     template <int G, int E>
@@ -221,12 +152,6 @@ struct ExplicitL {
     }
 };
 
-// true if [a, a + na) and [b, b + nb) (bytes) overlap
-bool overlap(const void* a, size_t na, const void* b, size_t nb) {
-    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
-    return x < y + nb && y < x + na;
-}
-
 }  // namespace
 
 extern "C" rbf_status rbf_apply_operators(rbf_ctx* ctx, int64_t N, const int64_t* offsets, const int32_t* idx,
@@ -237,16 +162,16 @@ extern "C" rbf_status rbf_apply_operators(rbf_ctx* ctx, int64_t N, const int64_t
     if (n_ops < 1 || n_ops > 4) return RBF_EINVAL;
     if (n_u > INT32_MAX + (int64_t)1) return RBF_EINVAL;  // indices are int32
     const size_t out_b = (size_t)n_ops * (size_t)N * sizeof(double);
-    if (overlap(out, out_b, u, (size_t)n_u * sizeof(double)) ||
-        overlap(out, out_b, w, (size_t)n_ops * (size_t)nnz * sizeof(double)))
+    if (ranges_overlap(out, out_b, u, (size_t)n_u * sizeof(double)) ||
+        ranges_overlap(out, out_b, w, (size_t)n_ops * (size_t)nnz * sizeof(double)))
         return RBF_EINVAL;
     RBF_HIP_CHECK(hipSetDevice(ctx->device));
     hipError_t e;
     switch (n_ops) {
-        case 1: e = dispatch_shape<ApplyL<1>::L>(n_max, N, ctx->stream, N, offsets, idx, w, nnz, u, n_u, out); break;
-        case 2: e = dispatch_shape<ApplyL<2>::L>(n_max, N, ctx->stream, N, offsets, idx, w, nnz, u, n_u, out); break;
-        case 3: e = dispatch_shape<ApplyL<3>::L>(n_max, N, ctx->stream, N, offsets, idx, w, nnz, u, n_u, out); break;
-        default: e = dispatch_shape<ApplyL<4>::L>(n_max, N, ctx->stream, N, offsets, idx, w, nnz, u, n_u, out); break;
+        case 1: e = dispatch_row_shape<ApplyL<1>::L>(n_max, N, ctx->stream, N, offsets, idx, w, nnz, u, n_u, out); break;
+        case 2: e = dispatch_row_shape<ApplyL<2>::L>(n_max, N, ctx->stream, N, offsets, idx, w, nnz, u, n_u, out); break;
+        case 3: e = dispatch_row_shape<ApplyL<3>::L>(n_max, N, ctx->stream, N, offsets, idx, w, nnz, u, n_u, out); break;
+        default: e = dispatch_row_shape<ApplyL<4>::L>(n_max, N, ctx->stream, N, offsets, idx, w, nnz, u, n_u, out); break;
     }
     return e == hipSuccess ? RBF_OK : RBF_EHIP;
 }
@@ -262,9 +187,9 @@ extern "C" rbf_status rbf_explicit_step(rbf_ctx* ctx, int64_t N, int d, const in
     // Neumann rows need w_grad and normals; given neither, every Neumann row gets NaN
     if ((w_grad == nullptr) != (normals == nullptr)) return RBF_EINVAL;
     const size_t nb = (size_t)N * sizeof(double);
-    if (overlap(u_new, nb, u, nb) || overlap(u_new, nb, w_lap, (size_t)nnz * sizeof(double))) return RBF_EINVAL;
+    if (ranges_overlap(u_new, nb, u, nb) || ranges_overlap(u_new, nb, w_lap, (size_t)nnz * sizeof(double))) return RBF_EINVAL;
     RBF_HIP_CHECK(hipSetDevice(ctx->device));
-    const hipError_t e = dispatch_shape<ExplicitL>(n_max, N, ctx->stream, N, d, offsets, idx, nnz, w_lap, w_grad,
+    const hipError_t e = dispatch_row_shape<ExplicitL>(n_max, N, ctx->stream, N, d, offsets, idx, nnz, w_lap, w_grad,
                                                    kind, normals, g, s, u, dt, u_new);
     return e == hipSuccess ? RBF_OK : RBF_EHIP;
 }

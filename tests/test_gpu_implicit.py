@@ -1,0 +1,200 @@
+"""GPU implicit solution (Sec. 2.3.2, Sec. 5) against the oracle.
+
+rbf_assemble_implicit is compared entry by entry with oracle/implicit.py
+(interior and Dirichlet rows are copies: bit-equal; Neumann rows sum d
+products: the rounding bound 2 d eps sum_l |n_l w_l|).  rbf_bicgstab is
+compared with the oracle's direct solve of the oracle's system: the residual
+the solver monitors is recomputed on the host, and the solution must agree
+with the direct one to the accuracy the residual implies.  The whole GPU path
+(stencils, weights, assembly, BiCGStab) repeats the manufactured Poisson
+problem of Sec. 5 at the paper's convergence rate.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import nodesets as ns
+from oracle import implicit, knn, poisson, rbffd
+import heat_cases as hc
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(np.float64).eps
+
+
+def _rb():
+    import paper_1912_13282_amd as rb
+    return rb
+
+
+def _t(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def _annulus_problem(h, d=2, n=30, P=3, neumann=True, seed=5):
+    nd = ns.annulus(h, seed, d=d)
+    X = nd.X
+    r = np.linalg.norm(X, axis=1)
+    inner = nd.is_boundary & (r < 0.75)
+    kind = np.where(nd.is_boundary, hc.DIRICHLET, hc.INTERIOR).astype(np.uint8)
+    if neumann:
+        kind[inner] = hc.NEUMANN
+    normals = np.zeros((nd.N, d))
+    normals[inner] = -X[inner] / r[inner, None]
+    ops = ("lap", "dx", "dy", "dz")[:d + 1]
+    off, idx = knn.knn_exact(X, n)
+    W, st = rbffd.weights(X, off, idx, P, ops)
+    assert np.all(st == 0)
+    u0 = poisson.u0(X)
+    grad = np.stack([math.pi * np.cos(math.pi * X[:, a]) * np.prod(np.sin(math.pi * np.delete(X, a, axis=1)), axis=1)
+                     for a in range(d)], axis=1)
+    g = np.where(kind == hc.NEUMANN, np.sum(normals * grad, axis=1), u0)
+    f = poisson.lap_u0(X)
+    return nd, kind, normals, off, idx.astype(np.int32), W, f, g, u0
+
+
+@pytest.mark.parametrize("d", [2, 3])
+def test_assemble_implicit_parity(gpu, d):
+    rb = _rb()
+    nd, kind, normals, off, idx, W, f, g, _ = _annulus_problem(0.05 if d == 2 else 0.15, d=d,
+                                                                n=30 if d == 2 else 35, P=3)
+    vo, ro = implicit.assemble(off, idx, W[0], W[1:], kind, normals, f=f, g=g)
+    Wt = _t(W, gpu)
+    vals, rhs = rb.assemble_implicit(_t(off, gpu), _t(idx, gpu), Wt[0], _t(kind, gpu), w_grad=Wt[1:],
+                                     normals=_t(normals, gpu), f=_t(f, gpu), g=_t(g, gpu))
+    vg, rg = vals.cpu().numpy(), rhs.cpu().numpy()
+    assert np.array_equal(rg, ro)
+    row = np.repeat(np.arange(nd.N), np.diff(off))
+    ne = kind[row] == hc.NEUMANN
+    assert np.array_equal(vg[~ne], vo[~ne])
+    bound = 2 * d * EPS * sum(np.abs(normals[row, l] * W[1 + l]) for l in range(d))
+    assert np.all(np.abs(vg[ne] - vo[ne]) <= bound[ne])
+    # f and g omitted: zero right-hand side
+    _, r0 = rb.assemble_implicit(_t(off, gpu), _t(idx, gpu), Wt[0], _t(kind, gpu), w_grad=Wt[1:],
+                                 normals=_t(normals, gpu))
+    assert torch.count_nonzero(r0).item() == 0
+
+
+def test_assemble_implicit_invalid_rows(gpu):
+    rb = _rb()
+    nd, kind, normals, off, idx, W, f, g, _ = _annulus_problem(0.1)
+    kind = kind.copy()
+    idx2 = idx.copy()
+    inter = np.where(kind == hc.INTERIOR)[0]
+    dirich = np.where(kind == hc.DIRICHLET)[0]
+    neu = np.where(kind == hc.NEUMANN)[0]
+    kind[inter[0]] = 9
+    idx2[off[dirich[0]]] = idx2[off[dirich[0]] + 1]   # position 0 not the node itself
+    idx2[off[neu[0]]] = idx2[off[neu[0]] + 1]
+    Wt = _t(W, gpu)
+    vals, rhs = rb.assemble_implicit(_t(off, gpu), _t(idx2, gpu), Wt[0], _t(kind, gpu), w_grad=Wt[1:],
+                                     normals=_t(normals, gpu), f=_t(f, gpu), g=_t(g, gpu))
+    vg, rg = vals.cpu().numpy(), rhs.cpu().numpy()
+    bad = [inter[0], dirich[0], neu[0]]
+    assert np.all(np.isnan(rg[bad]))
+    for i in bad:
+        assert np.all(np.isnan(vg[off[i]:off[i + 1]]))
+    good = np.setdiff1d(np.arange(nd.N), bad)
+    assert not np.any(np.isnan(rg[good]))
+    # Neumann rows without gradient weights
+    _, r2 = rb.assemble_implicit(_t(off, gpu), _t(idx, gpu), Wt[0], _t(np.where(kind == 9, 0, kind).astype(np.uint8),
+                                                                       gpu), f=_t(f, gpu), g=_t(g, gpu))
+    assert np.all(np.isnan(r2.cpu().numpy()[neu]))
+
+
+def _scaled_residual(off, idx, vals, rhs, x, jacobi=True):
+    M = implicit.matrix(off, idx, vals)
+    dinv = 1.0 / M.diagonal() if jacobi else np.ones(M.shape[0])
+    return np.linalg.norm(dinv * (rhs - M @ x)) / np.linalg.norm(dinv * rhs)
+
+
+# 2D with Neumann rows needs the Jacobi scaling (about 4,200 iterations here);
+# the Dirichlet problems converge in a few hundred either way
+@pytest.mark.parametrize("d,precond,neumann", [(2, "jacobi", True), (2, "none", False), (3, "jacobi", False),
+                                               (3, "none", False)])
+def test_bicgstab_parity_with_direct_solve(gpu, d, precond, neumann):
+    rb = _rb()
+    nd, kind, normals, off, idx, W, f, g, u0 = _annulus_problem(0.025 if d == 2 else 0.12, d=d,
+                                                                 n=30 if d == 2 else 35, P=3, neumann=neumann)
+    vals, rhs = implicit.assemble(off, idx, W[0], W[1:], kind, normals, f=f, g=g)
+    ud = implicit.solve(off, idx, vals, rhs)
+    tol = 1e-12
+    n_max = int(np.diff(off).max())
+    x, info = rb.bicgstab(_t(off, gpu), _t(idx, gpu), _t(vals, gpu), n_max, _t(rhs, gpu), tol=tol, max_iter=20000,
+                          precond=precond)
+    assert info["status"] == rb.SOLVE_CONVERGED, info
+    xh = x.cpu().numpy()
+    # the monitored (recursively updated) residual and the true one agree to rounding
+    res = _scaled_residual(off, idx, vals, rhs, xh, jacobi=precond == "jacobi")
+    assert res <= 10 * tol, (res, info)
+    assert info["residual"] <= tol
+    M = implicit.matrix(off, idx, vals)
+    # the unscaled residual recomputed on the host, to the rounding of forming r - M x
+    # (n-term sums of |M||x| plus |r|, in another order on each side)
+    n_row = int(np.diff(off).max())
+    slack = 2 * (n_row + 2) * EPS * np.linalg.norm(abs(M) @ np.abs(xh) + np.abs(rhs)) / np.linalg.norm(rhs)
+    assert abs(info["true_residual"] - np.linalg.norm(rhs - M @ xh) / np.linalg.norm(rhs)) <= slack
+    # the direct solution, to the accuracy that residual allows (condition number below 1e5 here)
+    assert np.abs(xh - ud).max() <= 1e5 * 10 * tol * np.abs(ud).max(), np.abs(xh - ud).max()
+    assert np.abs(xh - u0).max() < 0.05
+    # deterministic: a second solve is bit-identical
+    x2, info2 = rb.bicgstab(_t(off, gpu), _t(idx, gpu), _t(vals, gpu), n_max, _t(rhs, gpu), tol=tol, max_iter=20000,
+                            precond=precond)
+    assert torch.equal(x, x2) and info2["iterations"] == info["iterations"]
+
+
+def test_bicgstab_outcomes(gpu):
+    rb = _rb()
+    nd, kind, normals, off, idx, W, f, g, _ = _annulus_problem(0.05)
+    vals, rhs = implicit.assemble(off, idx, W[0], W[1:], kind, normals, f=f, g=g)
+    n_max = int(np.diff(off).max())
+    to = lambda a: _t(a, gpu)  # noqa: E731
+    # iteration limit
+    x, info = rb.bicgstab(to(off), to(idx), to(vals), n_max, to(rhs), tol=1e-14, max_iter=3)
+    assert info["status"] == rb.SOLVE_MAXITER and info["iterations"] == 3
+    # the exact solution as the initial guess: converged without iterating
+    ud = implicit.solve(off, idx, vals, rhs)
+    x, info = rb.bicgstab(to(off), to(idx), to(vals), n_max, to(rhs), x=to(ud), tol=1e-6)
+    assert info["status"] == rb.SOLVE_CONVERGED and info["iterations"] == 0
+    assert np.array_equal(x.cpu().numpy(), ud)
+    # zero right-hand side from zero: converged at once, x stays zero
+    x, info = rb.bicgstab(to(off), to(idx), to(vals), n_max, torch.zeros(nd.N, dtype=torch.float64, device=gpu))
+    assert info["status"] == rb.SOLVE_CONVERGED and info["iterations"] == 0 and torch.count_nonzero(x).item() == 0
+    # a zero diagonal entry with Jacobi scaling
+    v2 = vals.copy()
+    i = np.where(kind == hc.INTERIOR)[0][3]
+    v2[off[i]] = 0.0
+    x, info = rb.bicgstab(to(off), to(idx), to(v2), n_max, to(rhs), precond="jacobi")
+    assert info["status"] == rb.SOLVE_BADDIAG
+    # non-finite input: breakdown, never a hang
+    r2 = rhs.copy()
+    r2[5] = np.nan
+    x, info = rb.bicgstab(to(off), to(idx), to(vals), n_max, to(r2))
+    assert info["status"] == rb.SOLVE_BREAKDOWN
+    with pytest.raises(rb.RbfError):
+        rb.bicgstab(to(off), to(idx), to(vals), n_max, to(rhs), precond="ilu")
+
+
+def test_gpu_poisson_at_the_papers_rate(gpu):
+    """Sec. 5 on the GPU: annulus, u_0 = prod sin(pi x_a), n = 9 in 2D with degree 2;
+    stencils, weights, assembly and BiCGStab on the device; error ~ N^(-1)."""
+    rb = _rb()
+    Ns, errs = [], []
+    for h in (0.02, 0.01, 0.005):
+        nd = ns.annulus(h, 5, d=2)
+        N, n = nd.N, 9
+        X = _t(nd.X, gpu)
+        off = _t(ns.offsets_from_sizes(np.full(N, n, dtype=np.int64)), gpu)
+        idx = rb.select_stencils(X, off, n)
+        w, st = rb.compute_weights(X, off, idx, n, 2, ("lap",))
+        assert int((st != 0).sum()) == 0
+        kind = _t(np.where(nd.is_boundary, hc.DIRICHLET, hc.INTERIOR).astype(np.uint8), gpu)
+        u0 = poisson.u0(nd.X)
+        vals, rhs = rb.assemble_implicit(off, idx, w[0], kind, f=_t(poisson.lap_u0(nd.X), gpu), g=_t(u0, gpu))
+        x, info = rb.bicgstab(off, idx, vals, n, rhs, tol=1e-11, max_iter=50000)
+        assert info["status"] == rb.SOLVE_CONVERGED, info
+        Ns.append(N)
+        errs.append(float(np.abs(x.cpu().numpy() - u0).max()))
+    slope = np.polyfit(np.log(Ns), np.log(errs), 1)[0]
+    assert -1.4 < slope < -0.7, (Ns, errs, slope)
