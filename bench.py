@@ -51,12 +51,19 @@ PEAK_BF16_TFLOPS = 2500.0   # dense bf16 MFMA
 PEAK_HBM_GBS = 8000.0
 ORD = {"lap": 2, "dx": 1, "dy": 1, "dz": 1}
 
-# Kernel sources of the weights path; the HBM traffic recorded under profiles/
-# belongs to the build whose sources hash to the recorded value.
-WEIGHTS_SOURCES = ("include/rbffd.h", "paper_1912_13282_amd/csrc/common.hpp", "paper_1912_13282_amd/csrc/wsolve.hpp",
-                   "paper_1912_13282_amd/csrc/weights_kernels.hpp", "paper_1912_13282_amd/csrc/weights.hip",
-                   "paper_1912_13282_amd/csrc/wcls_56.hip")
-TRAFFIC_FILE = "profiles/traffic_weights_cube_minus_sphere_3d.txt"
+# HBM traffic of each workload's dominant kernel, from FETCH_SIZE / WRITE_SIZE
+# passes recorded under profiles/; valid while that kernel's sources hash to the
+# recorded value.
+CSRC = "paper_1912_13282_amd/csrc/"
+TRAFFIC = {
+    "cube_sphere3d": ("profiles/traffic_weights_cube_minus_sphere_3d.txt",
+                      [CSRC + f for f in ("common.hpp", "wsolve.hpp", "weights_kernels.hpp", "weights.hip",
+                                          "wcls_56.hip")]),
+    "explicit": ("profiles/traffic_apply_explicit_heat_cube_minus_sphere_3d.txt",
+                 [CSRC + f for f in ("common.hpp", "rowdot.hpp", "apply.hip")]),
+    "poisson3d": ("profiles/traffic_spmv_poisson_annulus_3d.txt",
+                  [CSRC + f for f in ("common.hpp", "rowdot.hpp", "implicit.hip")]),
+}
 
 
 def weights_flops(n, m, d, R):
@@ -81,18 +88,21 @@ SURROGATE_FLOPS = 2.0 * (32 * 128 + 128 * 128 * 2 + 128 * 16)   # MFMA work per 
 SURROGATE_BYTES = 8 + 15 * 4 + 15 * 8 + 1 + 16                  # offsets, idx, w, status, centre coordinates
 
 
-def weights_source_hash() -> str:
+def source_hash(files) -> str:
     h = hashlib.sha256()
-    for f in WEIGHTS_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(form: str):
-    """HBM bytes per launch of the dominant weights kernel from the committed
+def recorded_traffic(workload: str, form: str | None = None):
+    """HBM bytes per launch of the workload's dominant kernel from the committed
     FETCH_SIZE / WRITE_SIZE passes, or None if absent or taken on other sources."""
-    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if workload not in TRAFFIC:
+        return None
+    path, files = TRAFFIC[workload]
+    path = os.path.join(ROOT, path)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -101,7 +111,7 @@ def recorded_traffic(form: str):
             if ":" in line and not line.startswith("#"):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("source_hash") != weights_source_hash() or kv.get("form") != form:
+    if kv.get("source_hash") != source_hash(files) or (form is not None and kv.get("form") != form):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -301,7 +311,7 @@ def bench_uniform(a, torch, rb, B, name):
         kernel = "k_weights_f64<56>"
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP64_TFLOPS,
-                "traffic": recorded_traffic(a.form) if name == "cube_sphere3d" else None,
+                "traffic": recorded_traffic(name, a.form),
                 "kernel": kernel, "flop_per_stencil": flop, "stencils_per_launch": N}
     phases_roofline = {}
     for ph_name, per in (("select_stencils", knn_bytes(n, d)), ("assemble_csr", csr_bytes(n, R))):
@@ -624,7 +634,7 @@ def bench_explicit(a, torch, rb, B):
     res["metric"] = "explicit Euler node updates/s (one step + evaluation of four operators)"
     res["unit"] = "nodes/s"
     res["roofline"] = {"bound": "hbm", "achieved": gbs_a, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                       "frac": gbs_a / PEAK_HBM_GBS, "traffic": None,
+                       "frac": gbs_a / PEAK_HBM_GBS, "traffic": recorded_traffic("explicit"),
                        "kernel": "k_apply<8,5,4>", "bytes_per_node": ab / N, "nodes_per_launch": N}
     res["phases_roofline"] = {"explicit_step": {"bound": "hbm", "kernel": "k_explicit<8,5>", "bytes": eb,
                                                 "achieved_GBs": gbs_e, "frac": gbs_e / PEAK_HBM_GBS},
@@ -742,7 +752,7 @@ def bench_poisson(a, torch, rb, B):
     res["metric"] = "Poisson nodes solved/s (stencils + weights + assembly + BiCGStab)"
     res["unit"] = "nodes/s"
     res["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                       "frac": gbs / PEAK_HBM_GBS, "traffic": None,
+                       "frac": gbs / PEAK_HBM_GBS, "traffic": recorded_traffic(a.workload),
                        "kernel": f"BiCGStab iteration (k_vec<P>, k_spmv<8,{(n + 7) // 8},V>, k_vec<S>, "
                                  f"k_spmv<8,{(n + 7) // 8},T>, k_vec<X>)",
                        "bytes_per_row_per_iteration": bicgstab_bytes_per_row(n), "rows": N, "iterations": it}

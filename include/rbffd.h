@@ -294,7 +294,7 @@ typedef struct rbf_solve_info {
  * iteration); the call waits for the context stream every 16 iterations and
  * on return, when *info (host memory, may be NULL) is filled.  Deterministic:
  * every dot product is reduced in a fixed order.  Workspace:
- * rbf_bicgstab_workspace (7 N + 8192 float64 values).
+ * rbf_bicgstab_workspace (7 N + 4,096 float64 values and 256 bytes).
  * ------------------------------------------------------------------------ */
 rbf_status rbf_bicgstab_workspace(int64_t N, size_t* bytes);
 rbf_status rbf_bicgstab(rbf_ctx* ctx, int64_t N, const int64_t* offsets, const int32_t* idx,

@@ -69,7 +69,8 @@ __global__ __launch_bounds__(256) void k_assemble(int64_t N, int d, const int64_
 
 // ------------------------------------------------------------------ solver
 constexpr int RUNNING = -1;
-constexpr int NBMAX = 2048;      // blocks of every solver kernel (bounds the block sums)
+constexpr int NBMAX = 2048;      // blocks of the row-product kernels (bounds the block sums)
+constexpr int NBVEC = 2048;      // blocks of the vector kernels
 constexpr int CHECK_EVERY = 16;  // iterations between host checks
 
 struct SolveState {
@@ -157,7 +158,7 @@ enum { SP_R0, SP_V, SP_T, SP_TRUE };
 //   SP_V:    v = D^-1 M p;  rh . v
 //   SP_T:    t = D^-1 M s;  t . s, t . t
 //   SP_TRUE: |b - M x|^2, |b|^2 (the unscaled residual of the result)
-template <int G, int E, int MODE>
+template <int G, int E, int U, int MODE>
 __global__ __launch_bounds__(256) void k_spmv(SolveArgs a) {
     SolveState* st = a.st;
     if (MODE == SP_V || MODE == SP_T) {
@@ -168,16 +169,54 @@ __global__ __launch_bounds__(256) void k_spmv(SolveArgs a) {
     const int gl = threadIdx.x & (G - 1);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x / G;
     double c0 = 0.0, c1 = 0.0;
-    for (int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; row < a.N; row += stride) {
-        const int64_t off = a.offsets[row], end = a.offsets[row + 1];
-        bool bad = off < 0 || end < off || end > a.nnz;
-        const int64_t n = bad ? 0 : end - off;
-        double acc[1] = {0.0};
-        row_dot_partial<G, E, 1>(a.idx, a.vals, 0, off, n, xin, a.N, gl, acc, bad);
-        bad = group_any<G>(bad);
-        double ax = group_sum<G>(acc[0]);
-        if (bad) ax = kNaN;
-        if (gl == 0) {
+    // U rows (row0, row0 + stride, ...) per pass: their loads are in flight together
+    for (int64_t row0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; row0 < a.N; row0 += U * stride) {
+        int64_t off[U], n[U];
+        bool bad[U];
+        double acc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t row = row0 + u * stride;
+            const bool in = row < a.N;
+            const int64_t o = in ? a.offsets[row] : 0, e = in ? a.offsets[row + 1] : 0;
+            bad[u] = o < 0 || e < o || e > a.nnz;
+            off[u] = o;
+            n[u] = bad[u] ? 0 : e - o;
+            acc[u] = 0.0;
+        }
+        const int64_t nmax = U == 1 ? n[0] : (n[0] > n[U - 1] ? n[0] : n[U - 1]);
+        for (int64_t base = 0; base < nmax; base += G * E) {
+            int j[U][E];
+            double wv[U][E], xv[U][E];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int q = 0; q < E; ++q) {
+                    const int64_t e = base + gl + G * q;
+                    j[u][q] = (e < n[u]) ? a.idx[off[u] + e] : 0;
+                    wv[u][q] = (e < n[u]) ? a.vals[off[u] + e] : 0.0;
+                }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int q = 0; q < E; ++q) {
+                    const int64_t e = base + gl + G * q;
+                    const bool ok = j[u][q] >= 0 && (int64_t)j[u][q] < a.N;
+                    bad[u] |= (e < n[u]) && !ok;
+                    xv[u][q] = (e < n[u] && ok) ? xin[j[u][q]] : 0.0;
+                }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int q = 0; q < E; ++q) acc[u] = fma(wv[u][q], xv[u][q], acc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t row = row0 + u * stride;
+            const bool rbad = group_any<G>(bad[u]);
+            double ax = group_sum<G>(acc[u]);
+            if (rbad) ax = kNaN;
+            if (gl != 0 || row >= a.N) continue;
             if (MODE == SP_R0) {
                 const double di = a.dinv[row], bi = a.b[row];
                 const double ri = di * (bi - ax);
@@ -255,11 +294,23 @@ __global__ __launch_bounds__(256) void k_reduce(SolveArgs a, int nb) {
         return;
     }
     __shared__ double red[2][4];
-    double s0 = 0.0, s1 = 0.0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        s0 += a.part[2 * b];
-        s1 += a.part[2 * b + 1];
+    // eight independent accumulators per thread keep eight loads in flight;
+    // they are combined in a fixed order
+    double q0[8], q1[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) q0[k] = q1[k] = 0.0;
+    for (int b0 = threadIdx.x; b0 < nb; b0 += 8 * 256) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int b = b0 + k * 256;
+            if (b < nb) {
+                q0[k] += a.part[2 * b];
+                q1[k] += a.part[2 * b + 1];
+            }
+        }
     }
+    double s0 = ((q0[0] + q0[1]) + (q0[2] + q0[3])) + ((q0[4] + q0[5]) + (q0[6] + q0[7]));
+    double s1 = ((q1[0] + q1[1]) + (q1[2] + q1[3])) + ((q1[4] + q1[5]) + (q1[6] + q1[7]));
     s0 = wave_sum_d(s0);
     s1 = wave_sum_d(s1);
     const int wv = threadIdx.x >> 6;
@@ -317,9 +368,9 @@ __global__ __launch_bounds__(256) void k_reduce(SolveArgs a, int nb) {
     }
 }
 
-unsigned blocks_for(int64_t threads) {
+unsigned blocks_for(int64_t threads, int64_t cap) {
     const int64_t b = (threads + 255) / 256;
-    return (unsigned)(b < NBMAX ? (b > 0 ? b : 1) : NBMAX);
+    return (unsigned)(b < cap ? (b > 0 ? b : 1) : cap);
 }
 
 template <int G, int E>
@@ -331,35 +382,61 @@ struct DiagL {
 };
 
 // the solver kernels with rows of at most n_max entries
-template <int G, int E>
+template <int G, int E, int U>
 struct SolverL {
-    static hipError_t launch(dim3, hipStream_t s, SolveArgs a, int what) {
-        const dim3 gr(blocks_for(a.N * G)), gv(blocks_for(a.N)), b(256), one(1);
+    static hipError_t launch(hipStream_t s, SolveArgs a, int what) {
+        const dim3 gr(blocks_for(a.N * G, NBMAX)), gv(blocks_for(a.N, NBVEC)), b(256), one(1);
         const int nr = (int)gr.x, nv = (int)gv.x;
         switch (what) {
             case 0:
-                hipLaunchKernelGGL((k_spmv<G, E, SP_R0>), gr, b, 0, s, a);
+                hipLaunchKernelGGL((k_spmv<G, E, U, SP_R0>), gr, b, 0, s, a);
                 hipLaunchKernelGGL((k_reduce<RD_R0>), one, b, 0, s, a, nr);
                 break;
             case 1:
                 hipLaunchKernelGGL((k_vec<VP>), gv, b, 0, s, a);
-                hipLaunchKernelGGL((k_spmv<G, E, SP_V>), gr, b, 0, s, a);
+                hipLaunchKernelGGL((k_spmv<G, E, U, SP_V>), gr, b, 0, s, a);
                 hipLaunchKernelGGL((k_reduce<RD_V>), one, b, 0, s, a, nr);
                 hipLaunchKernelGGL((k_vec<VS>), gv, b, 0, s, a);
                 hipLaunchKernelGGL((k_reduce<RD_S>), one, b, 0, s, a, nv);
-                hipLaunchKernelGGL((k_spmv<G, E, SP_T>), gr, b, 0, s, a);
+                hipLaunchKernelGGL((k_spmv<G, E, U, SP_T>), gr, b, 0, s, a);
                 hipLaunchKernelGGL((k_reduce<RD_T>), one, b, 0, s, a, nr);
                 hipLaunchKernelGGL((k_vec<VX>), gv, b, 0, s, a);
                 hipLaunchKernelGGL((k_reduce<RD_X>), one, b, 0, s, a, nv);
                 break;
             default:
-                hipLaunchKernelGGL((k_spmv<G, E, SP_TRUE>), gr, b, 0, s, a);
+                hipLaunchKernelGGL((k_spmv<G, E, U, SP_TRUE>), gr, b, 0, s, a);
                 hipLaunchKernelGGL((k_reduce<RD_TRUE>), one, b, 0, s, a, nr);
                 break;
         }
         return hipGetLastError();
     }
 };
+
+// Row-product shape of the solver (measured on 1M-row systems): two lanes per
+// row for rows of at most 10 entries, eight lanes with two rows in flight up
+// to 64, then 16 and 64 lanes.  Longer rows than n_max are still summed whole.
+hipError_t solver_launch(int n_max, hipStream_t s, SolveArgs a, int what) {
+    switch (n_max <= 10 ? (n_max + 1) / 2 : 0) {
+        case 1: return SolverL<2, 1, 1>::launch(s, a, what);
+        case 2: return SolverL<2, 2, 1>::launch(s, a, what);
+        case 3: return SolverL<2, 3, 1>::launch(s, a, what);
+        case 4: return SolverL<2, 4, 1>::launch(s, a, what);
+        case 5: return SolverL<2, 5, 1>::launch(s, a, what);
+        default: break;
+    }
+    switch (n_max <= 64 ? (n_max + 7) / 8 : 0) {
+        case 2: return SolverL<8, 2, 2>::launch(s, a, what);
+        case 3: return SolverL<8, 3, 2>::launch(s, a, what);
+        case 4: return SolverL<8, 4, 2>::launch(s, a, what);
+        case 5: return SolverL<8, 5, 2>::launch(s, a, what);
+        case 6: return SolverL<8, 6, 2>::launch(s, a, what);
+        case 7: return SolverL<8, 7, 2>::launch(s, a, what);
+        case 8: return SolverL<8, 8, 2>::launch(s, a, what);
+        default: break;
+    }
+    if (n_max <= 128) return SolverL<16, 8, 1>::launch(s, a, what);
+    return SolverL<64, 4, 1>::launch(s, a, what);
+}
 
 size_t solve_ws_bytes(int64_t N) {
     return rbf_align(sizeof(SolveState)) + rbf_align((size_t)NBMAX * 2 * sizeof(double)) +
@@ -431,7 +508,7 @@ extern "C" rbf_status rbf_bicgstab(rbf_ctx* ctx, int64_t N, const int64_t* offse
     RBF_LAUNCH_CHECK();
     if (dispatch_row_shape<DiagL>(n_max, N, s, a, precond == RBF_PRECOND_JACOBI ? 1 : 0) != hipSuccess)
         return RBF_EHIP;
-    if (dispatch_row_shape<SolverL>(n_max, N, s, a, 0) != hipSuccess) return RBF_EHIP;
+    if (solver_launch(n_max, s, a, 0) != hipSuccess) return RBF_EHIP;
 
     SolveState hs;
     int enqueued = 0;
@@ -441,10 +518,10 @@ extern "C" rbf_status rbf_bicgstab(rbf_ctx* ctx, int64_t N, const int64_t* offse
         if (hs.status != RUNNING || enqueued >= max_iter) break;
         const int chunk = max_iter - enqueued < CHECK_EVERY ? max_iter - enqueued : CHECK_EVERY;
         for (int k = 0; k < chunk; ++k)
-            if (dispatch_row_shape<SolverL>(n_max, N, s, a, 1) != hipSuccess) return RBF_EHIP;
+            if (solver_launch(n_max, s, a, 1) != hipSuccess) return RBF_EHIP;
         enqueued += chunk;
     }
-    if (dispatch_row_shape<SolverL>(n_max, N, s, a, 2) != hipSuccess) return RBF_EHIP;
+    if (solver_launch(n_max, s, a, 2) != hipSuccess) return RBF_EHIP;
     RBF_HIP_CHECK(hipMemcpyAsync(&hs, a.st, sizeof(hs), hipMemcpyDeviceToHost, s));
     RBF_HIP_CHECK(hipStreamSynchronize(s));
     if (info) {

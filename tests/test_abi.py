@@ -78,13 +78,16 @@ int main(void) {{
   F(rbf_domain_desc, n_max) F(rbf_domain_desc, op_mask) F(rbf_domain_desc, w) F(rbf_domain_desc, status)
   printf("rbf_plan size %zu\\n", sizeof(rbf_plan));
   F(rbf_plan, chunk) F(rbf_plan, waves_per_cu) F(rbf_plan, ms)
+  printf("rbf_solve_info size %zu\\n", sizeof(rbf_solve_info));
+  F(rbf_solve_info, status) F(rbf_solve_info, iterations) F(rbf_solve_info, residual) F(rbf_solve_info, true_residual)
   return 0;
 }}
 ''')
     exe = tmp_path / "lay"
     subprocess.run(["gcc", "-O0", "-o", str(exe), str(src)], check=True)
     out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
-    py = {"rbf_options": B.rbf_options, "rbf_domain_desc": B.rbf_domain_desc, "rbf_plan": B.rbf_plan}
+    py = {"rbf_options": B.rbf_options, "rbf_domain_desc": B.rbf_domain_desc, "rbf_plan": B.rbf_plan,
+          "rbf_solve_info": B.rbf_solve_info}
     for line in filter(None, out):
         T, f, v = line.split()
         if f == "size":
@@ -152,3 +155,27 @@ def test_more_host_argument_errors_without_gpu(lib_path):
     assert L.rbf_surrogate_load(None, None) == -1
     assert L.rbf_assemble_csr(None, ctypes.c_int64(1), None, None, None, 0, ctypes.c_int64(1), 1, None, None,
                               None) == -1
+    # explicit evaluation, implicit assembly and the solver
+    one = ctypes.c_int64(1)
+    assert L.rbf_apply_operators(None, one, None, None, None, 1, one, 1, None, one, None) == -1
+    assert L.rbf_explicit_step(None, one, 2, None, None, one, 1, None, None, None, None, None, None, None,
+                               ctypes.c_double(0.1), None) == -1
+    assert L.rbf_assemble_implicit(None, one, 2, None, None, one, None, None, None, None, None, None, None,
+                                   None) == -1
+    assert L.rbf_bicgstab_workspace(ctypes.c_int64(0), ctypes.byref(b)) == -1
+    assert L.rbf_bicgstab_workspace(ctypes.c_int64(1000), None) == -1
+    assert L.rbf_bicgstab_workspace(ctypes.c_int64(1000), ctypes.byref(b)) == 0
+    assert b.value >= 7 * 1000 * 8 + 4096 * 8
+    assert L.rbf_bicgstab(None, one, None, None, None, one, 1, None, None, ctypes.c_double(1e-8), 10, 1, None,
+                          ctypes.c_size_t(0), None) == -1
+
+
+def test_node_kind_and_solver_constants_match_the_binding():
+    from paper_1912_13282_amd import _binding as B
+    src = open(HEADER).read()
+    val = lambda name: int(re.search(r"#define " + name + r"\s+(\d+)", src).group(1))  # noqa: E731
+    assert (val("RBF_NODE_INTERIOR"), val("RBF_NODE_DIRICHLET"), val("RBF_NODE_NEUMANN")) == \
+        (B.NODE_INTERIOR, B.NODE_DIRICHLET, B.NODE_NEUMANN)
+    assert (val("RBF_SOLVE_CONVERGED"), val("RBF_SOLVE_MAXITER"), val("RBF_SOLVE_BREAKDOWN"),
+            val("RBF_SOLVE_BADDIAG")) == (B.SOLVE_CONVERGED, B.SOLVE_MAXITER, B.SOLVE_BREAKDOWN, B.SOLVE_BADDIAG)
+    assert (val("RBF_PRECOND_NONE"), val("RBF_PRECOND_JACOBI")) == (B.PRECOND["none"], B.PRECOND["jacobi"])

@@ -144,6 +144,28 @@ def test_bicgstab_parity_with_direct_solve(gpu, d, precond, neumann):
     assert torch.equal(x, x2) and info2["iterations"] == info["iterations"]
 
 
+def test_bicgstab_csr_with_ragged_rows(gpu):
+    """The solver on CSR input: columns ascending (the diagonal anywhere in a row),
+    explicit zeros dropped so that Dirichlet rows hold one entry."""
+    rb = _rb()
+    nd, kind, normals, off, idx, W, f, g, u0 = _annulus_problem(0.025, neumann=False)
+    vals, rhs = implicit.assemble(off, idx, W[0], W[1:], kind, normals, f=f, g=g)
+    M = implicit.matrix(off, idx, vals)
+    M.eliminate_zeros()
+    M.sort_indices()
+    lens = np.diff(M.indptr)
+    assert lens.min() == 1 and lens.max() == 30
+    ud = implicit.solve(off, idx, vals, rhs)
+    tol = 1e-12
+    x, info = rb.bicgstab(_t(M.indptr.astype(np.int64), gpu), _t(M.indices.astype(np.int32), gpu), _t(M.data, gpu),
+                          30, _t(rhs, gpu), tol=tol, max_iter=20000, precond="jacobi")
+    assert info["status"] == rb.SOLVE_CONVERGED, info
+    xh = x.cpu().numpy()
+    dinv = 1.0 / M.diagonal()
+    assert np.linalg.norm(dinv * (rhs - M @ xh)) / np.linalg.norm(dinv * rhs) <= 10 * tol
+    assert np.abs(xh - ud).max() <= 1e5 * 10 * tol * np.abs(ud).max()
+
+
 def test_bicgstab_outcomes(gpu):
     rb = _rb()
     nd, kind, normals, off, idx, W, f, g, _ = _annulus_problem(0.05)
