@@ -6,7 +6,7 @@
  *   1. stencil selection: for each node the n_i closest nodes, itself first;
  *   2. RBF-FD weights: for each stencil the augmented polyharmonic-spline plus
  *      monomial system of eq. (rbf-system-aug), solved for the Laplacian and
- *      first-derivative weights;
+ *      first-derivative weights (or the GWLS weights of Sec. 2.2.1);
  *   3. the sparse operator in CSR form (at most sum n_i nonzeros);
  *   4. explicit evaluation of the operators on a field and the explicit Euler
  *      time step built from it (Sec. 2.3.1);
@@ -138,6 +138,30 @@ rbf_status rbf_compute_weights(rbf_ctx* ctx, const double* X, int64_t N, int d,
                                const int64_t* offsets, const int32_t* idx, int64_t nnz,
                                int n_max, int degree, unsigned op_mask,
                                const rbf_options* opt, double* w, int8_t* status);
+
+/* weight functions of the GWLS engine */
+#define RBF_WLS_UNIT      0   /* omega = 1: plain least squares                        */
+#define RBF_WLS_GAUSSIAN  1   /* omega(x) = exp(-|x|^2 / sigma^2) on the scaled offsets */
+
+/* ------------------------------------------------------------------------ *
+ * GWLS weights, Sec. 2.2.1 (the paper's second approximation engine).
+ *
+ * Basis: the monomials of total degree <= degree (m = C(degree + d, d)) at the
+ * scaled offsets x_j = (p_j - p*) / s (s from opt->scale_mode, as for
+ * rbf_compute_weights); W = diag(omega(x_j)).  The weights of each operator are
+ * w = W y with y the minimum-norm solution of (W B)^T y = (L b)(0), eq. (wbsys),
+ * i.e. w^T = (L b)(0)^T (W B)^+ W, scaled back by s^-2 (LAP) or s^-1.  Solved by
+ * Householder QR of W B in float64, one stencil per wavefront.  A stencil whose
+ * W B is rank deficient (n_i < m included) gets RBF_ST_SINGULAR and NaN
+ * weights; accepted weights pass the FP64 reproduction check (opt->repro_tol).
+ * n_max <= 64, degree 0..4; weight_fn RBF_WLS_*, sigma > 0 for the Gaussian;
+ * opt may be NULL (defaults; its precision and phs_power are not used).
+ * status[N] may be NULL.  w: [popcount(op_mask)][nnz].  No workspace.
+ * ------------------------------------------------------------------------ */
+rbf_status rbf_compute_weights_wls(rbf_ctx* ctx, const double* X, int64_t N, int d,
+                                   const int64_t* offsets, const int32_t* idx, int64_t nnz,
+                                   int n_max, int degree, unsigned op_mask, int weight_fn,
+                                   double sigma, const rbf_options* opt, double* w, int8_t* status);
 
 /* ------------------------------------------------------------------------ *
  * CSR operator (Sec. 2.3.2, internal-node rows of eqs. implicit-start..end).

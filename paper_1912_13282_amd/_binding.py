@@ -86,6 +86,8 @@ _SIGS = {
     "rbf_get_plan": [_P, ctypes.POINTER(rbf_plan)],
     "rbf_apply_operators": [_P, _I64, _P, _P, _P, _I, _I64, _I, _P, _I64, _P],
     "rbf_explicit_step": [_P, _I64, _I, _P, _P, _I64, _I, _P, _P, _P, _P, _P, _P, _P, ctypes.c_double, _P],
+    "rbf_compute_weights_wls": [_P, _P, _I64, _I, _P, _P, _I64, _I, _I, _U, _I, ctypes.c_double,
+                                ctypes.POINTER(rbf_options), _P, _P],
     "rbf_assemble_implicit": [_P, _I64, _I, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P],
     "rbf_bicgstab_workspace": [_I64, ctypes.POINTER(_SZ)],
     "rbf_bicgstab": [_P, _I64, _P, _P, _P, _I64, _I, _P, _P, ctypes.c_double, _I, _I, _P, _SZ,
@@ -249,6 +251,34 @@ def assemble_csr(offsets: torch.Tensor, idx: torch.Tensor, w: torch.Tensor | Non
                                   _dev(row_ptr, torch.int64, "row_ptr"), _dev(col, torch.int32, "col"), pv),
            "rbf_assemble_csr")
     return row_ptr, col, vals
+
+
+# ------------------------------------------------------------------ GWLS engine
+WLS_WEIGHT = {"unit": 0, "gaussian": 1}
+
+
+def compute_weights_wls(X: torch.Tensor, offsets: torch.Tensor, idx: torch.Tensor, n_max: int, degree: int,
+                        ops=("lap",), weight: str = "gaussian", sigma: float = 1.0, w: torch.Tensor | None = None,
+                        status: torch.Tensor | None = None, ctx: Context | None = None, **opt):
+    """GWLS weights [len(ops), nnz] float64 (monomial basis, Sec. 2.2.1) and status int8 [N]."""
+    ctx = ctx or context(X.device)
+    N, d = X.shape
+    nnz = idx.numel()
+    ops = tuple(o for o in OPS if o in ops)
+    if weight not in WLS_WEIGHT:
+        raise RbfError(f"weight must be one of {sorted(WLS_WEIGHT)}")
+    if w is None:
+        w = torch.empty((len(ops), nnz), dtype=torch.float64, device=X.device)
+    if status is None:
+        status = torch.empty(N, dtype=torch.int8, device=X.device)
+    o = options(**opt)
+    _check(lib().rbf_compute_weights_wls(ctx._sync_stream(), _dev(X, torch.float64, "X"), N, d,
+                                         _dev(offsets, torch.int64, "offsets"), _dev(idx, torch.int32, "idx"), nnz,
+                                         int(n_max), int(degree), op_mask(ops), WLS_WEIGHT[weight], float(sigma),
+                                         ctypes.byref(o), _dev(w, torch.float64, "w"),
+                                         _dev(status, torch.int8, "status")),
+           "rbf_compute_weights_wls")
+    return w, status
 
 
 # ------------------------------------------------------------------ explicit evaluation
