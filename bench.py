@@ -22,6 +22,9 @@ Other workloads (the same JSON contract, one line each):
            minus B(0,1/2), u_0 = prod sin(pi x_a) on the boundary, n = 35 (3D) or
            9 (2D), degree 2, about 1M nodes; stencils, weights, implicit
            assembly and BiCGStab (Jacobi scaling, tol 1e-10) per step
+  wls      the GWLS engine (Sec. 2.2.1) on the default node set: monomials of degree
+           3, Gaussian weight (sigma 1 on the scaled offsets), four operators, with
+           kNN and CSR
   explicit explicit Euler steps of du/dt = lap u + 5 on the default node set
            (faces u = x, sphere zero flux), each followed by the evaluation of
            the four operators on the new field; weights computed beforehand
@@ -124,7 +127,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cube_sphere3d", choices=["cube_sphere3d", "mixed", "learned", "large3d", "explicit", "poisson3d", "poisson2d"])
+    ap.add_argument("--workload", default="cube_sphere3d", choices=["cube_sphere3d", "mixed", "learned", "large3d", "explicit", "poisson3d", "poisson2d", "wls"])
     ap.add_argument("--form", default="f32_ir", choices=["f32_ir", "f64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="time only the reported form")
@@ -559,6 +562,93 @@ def bench_learned(a, torch, rb, B):
     return out
 
 
+# ---------------------------------------------------------------- GWLS engine (Sec. 2.2.1)
+def wls_flops(n, m, R, d):
+    """Algorithmic FLOPs of one stencil's GWLS weights by Householder QR: the
+    factorisation of the n x m matrix W B (2 n m^2 - 2 m^3 / 3), per operator the
+    substitution with R^T (m^2) and the reflections applied to [z; 0] (4 n m - 2 m^2),
+    and the basis and weight-function values (about n (m + 2 d + 10))."""
+    return 2.0 * n * m * m - 2.0 * m ** 3 / 3.0 + R * (m * m + 4.0 * n * m - 2.0 * m * m) + n * (m + 2 * d + 10)
+
+
+def bench_wls(a, torch, rb, B):
+    import nodesets as ns
+    dev = torch.device("cuda:0")
+    wl = ns.workload("cube_sphere3d")
+    nd = wl["nodes"][0]
+    n, P, ops = wl["n"], wl["P"], wl["ops"]
+    N, d, R = nd.N, nd.d, len(ops)
+    m = math.comb(P + d, d)
+    sigma = 1.0
+    off_h = ns.offsets_from_sizes(np.full(N, n, dtype=np.int64))
+    nnz = int(off_h[-1])
+    X = torch.from_numpy(nd.X).to(dev)
+    offsets = torch.from_numpy(off_h).to(dev)
+    idx = torch.empty(nnz, dtype=torch.int32, device=dev)
+    ws = torch.empty(B.select_stencils_workspace(N, d, n), dtype=torch.uint8, device=dev)
+    w = torch.empty((R, nnz), dtype=torch.float64, device=dev)
+    status = torch.empty(N, dtype=torch.int8, device=dev)
+    row_ptr = torch.empty(N + 1, dtype=torch.int64, device=dev)
+    col = torch.empty(nnz, dtype=torch.int32, device=dev)
+    vals = torch.empty((R, nnz), dtype=torch.float64, device=dev)
+    ctx = rb.context(dev)
+    timer = Timer(torch, ["select_stencils", "compute_weights_wls", "assemble_csr"])
+
+    def step(e):
+        if e:
+            e[0].record(timer.stream)
+        rb.select_stencils(X, offsets, n, idx=idx, workspace=ws, ctx=ctx)
+        if e:
+            e[1].record(timer.stream)
+        rb.compute_weights_wls(X, offsets, idx, n, P, ops, weight="gaussian", sigma=sigma, w=w, status=status,
+                               ctx=ctx)
+        if e:
+            e[2].record(timer.stream)
+        rb.assemble_csr(offsets, idx, w, n, row_ptr=row_ptr, col=col, vals=vals, ctx=ctx)
+        if e:
+            e[3].record(timer.stream)
+
+    ms, wall, ph = timer.run(step, a.steps, a.warmup)
+    st = status.cpu().numpy()
+    print(f"[bench] wls: {ms:.3f} ms/step  phases {ph}", file=sys.stderr, flush=True)
+    flop = wls_flops(n, m, R, d)
+    achieved = flop * N / (ph["compute_weights_wls"] / 1e3) / 1e12
+    res = base_line(a, N / (ms / 1e3), ms, "f64",
+                    {"workload": "wls_cube_minus_sphere_3d", "N": N, "nnz": nnz, "n": n, "degree": P, "m": m,
+                     "ops": list(ops), "weight": "gaussian", "sigma": sigma,
+                     "step": "select_stencils + compute_weights_wls + assemble_csr"})
+    res["metric"] = "GWLS stencils/s (kNN + weights + CSR)"
+    res["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                       "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None, "kernel": "k_wls<20>",
+                       "flop_per_stencil": flop, "stencils_per_launch": N}
+    res["phases_ms"] = ph
+    res["wall_ms_per_step"] = wall
+    res["status_counts"] = status_counts(st)
+    if not a.no_cpu:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import knn as oknn
+        from oracle import wls as owls
+        sample = draw_sample(N, a.cpu_sample)
+        snap = w[:, torch.from_numpy(sample_positions(off_h, sample)).to(dev)].cpu().numpy()
+        with threadpool_limits(limits=1):
+            t = time.perf_counter()
+            c0 = time.process_time()
+            soff, sidx = oknn.knn_exact(nd.X, n, nodes=sample)
+            Wo = np.concatenate([owls.stencil_weights(nd.X[sidx[soff[i]:soff[i + 1]]], P, ops, owls.GAUSSIAN, sigma)
+                                 for i in range(sample.size)], axis=1)
+            dt = time.perf_counter() - t
+            cpu_s = time.process_time() - c0
+        res["cpu_baseline"] = {"value": sample.size / dt, "unit": "stencils/s", "cores": max(1, int(round(cpu_s / dt))),
+                               "kind": "oracle",
+                               "sample": f"{sample.size} seeded random nodes of the same workload (kNN against all "
+                                         f"{N} nodes + GWLS weights by pseudo-inverse), {dt:.1f} s wall, "
+                                         f"{cpu_s:.1f} s CPU, BLAS limited to one thread"}
+        res["error"] = {"scaled_max_err": scaled_err(snap, Wo, ops, np.repeat(nd.h[sample], n)),
+                        "tolerance": 1e-10, "sample": int(sample.size)}
+    return res
+
+
 # ---------------------------------------------------------------- explicit heat step
 def explicit_bytes(n_int, n_dir, n_neu, n, d, N):
     """Algorithmic HBM bytes of one explicit step: per node its kind, row offset,
@@ -815,6 +905,8 @@ def main():
         out = bench_mixed(a, torch, rb, B)
     elif a.workload == "explicit":
         out = bench_explicit(a, torch, rb, B)
+    elif a.workload == "wls":
+        out = bench_wls(a, torch, rb, B)
     elif a.workload in POISSON_CASES:
         out = bench_poisson(a, torch, rb, B)
     else:
