@@ -28,7 +28,12 @@ Readings of the paper (it leaves these open):
 Closed forms used for the right-hand side (phi(r) = r^k, r = ||x - x_j||):
     Laplacian: (lap phi_j)(0) = k (k + d - 2) ||x_j||^(k-2)
     d/dx_a:    (d_a phi_j)(0) = -k ||x_j||^(k-2) x_{j,a}
-    (lap q_l)(0) = 2 if q_l = x_a^2 else 0;  (d_a q_l)(0) = 1 if q_l = x_a else 0.
+    d2/dx_a dx_b: (d_ab phi_j)(0) = k ||x_j||^(k-2) delta_ab + k (k-2) ||x_j||^(k-4) x_{j,a} x_{j,b}
+               (0 at x_j = 0, where the second term vanishes in the limit)
+    (lap q_l)(0) = 2 if q_l = x_a^2 else 0;  (d_a q_l)(0) = 1 if q_l = x_a else 0;
+    (d_ab q_l)(0) = 2 if q_l = x_a^2 (a = b), 1 if q_l = x_a x_b (a != b), else 0.
+The second derivatives are the operators of the general second-order
+operator of eq. (gen-op), Sec. 3.3.
 """
 from __future__ import annotations
 
@@ -36,9 +41,10 @@ import math
 
 import numpy as np
 
-OPS = ("lap", "dx", "dy", "dz")
-OP_ORDER = {"lap": 2, "dx": 1, "dy": 1, "dz": 1}
+OPS = ("lap", "dx", "dy", "dz", "dxx", "dxy", "dxz", "dyy", "dyz", "dzz")
+OP_ORDER = {"lap": 2, "dx": 1, "dy": 1, "dz": 1, "dxx": 2, "dxy": 2, "dxz": 2, "dyy": 2, "dyz": 2, "dzz": 2}
 OP_AXIS = {"dx": 0, "dy": 1, "dz": 2}
+OP_AXES = {"dxx": (0, 0), "dxy": (0, 1), "dxz": (0, 2), "dyy": (1, 1), "dyz": (1, 2), "dzz": (2, 2)}
 
 
 def monomial_exponents(d: int, P: int) -> np.ndarray:
@@ -101,6 +107,17 @@ def assemble(Xs: np.ndarray, P: int, ops, phs_power: int = 3, scale: str = "max"
             for l in range(m):
                 if E[l].sum() == 2 and E[l].max() == 2:
                     RHS[:, n + l, c] = 2.0
+        elif op in OP_AXES:
+            a, b = OP_AXES[op]
+            rk4 = np.zeros_like(r)                                   # r^(k-4); its term is 0 at r = 0
+            np.power(r, k - 4.0, out=rk4, where=r > 0)
+            RHS[:, :n, c] = k * (a == b) * r ** (k - 2) + k * (k - 2) * rk4 * Xh[:, :, a] * Xh[:, :, b]
+            for l in range(m):
+                e = np.zeros(d, dtype=np.int64)
+                e[a] += 1
+                e[b] += 1
+                if np.array_equal(E[l], e):
+                    RHS[:, n + l, c] = 2.0 if a == b else 1.0
         else:
             a = OP_AXIS[op]
             RHS[:, :n, c] = -k * r ** (k - 2) * Xh[:, :, a]

@@ -24,7 +24,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .rbffd import OP_AXIS, OP_ORDER, monomial_exponents, scale_factor
+from .rbffd import OP_AXES, OP_AXIS, OP_ORDER, monomial_exponents, scale_factor
 
 UNIT, GAUSSIAN = 0, 1
 
@@ -45,6 +45,12 @@ def operator_of_basis(E: np.ndarray, ops) -> np.ndarray:
         for l in range(E.shape[0]):
             if op == "lap":
                 Lb[l, c] = 2.0 if (E[l].sum() == 2 and E[l].max() == 2) else 0.0
+            elif op in OP_AXES:
+                a, b = OP_AXES[op]
+                e = np.zeros(E.shape[1], dtype=np.int64)
+                e[a] += 1
+                e[b] += 1
+                Lb[l, c] = (2.0 if a == b else 1.0) if np.array_equal(E[l], e) else 0.0
             else:
                 Lb[l, c] = 1.0 if (E[l].sum() == 1 and E[l, OP_AXIS[op]] == 1) else 0.0
     return Lb
