@@ -22,7 +22,9 @@
  *     nnz = offsets[N].  Stencil i occupies idx[offsets[i] .. offsets[i+1]).
  *   - Weight arrays are operator-major: w[r * nnz + offsets[i] + j] is the
  *     weight of stencil node j of node i for the r-th operator selected in
- *     op_mask, operators ordered LAP, DX, DY, DZ.
+ *     op_mask, operators ordered LAP, DX, DY, DZ, DXX, DXY, DXZ, DYY, DYZ, DZZ.
+ *     One weights call computes at most four operators (one local solve
+ *     serves them all); operators along z need d = 3.
  *   - Every call is asynchronous on the context's HIP stream.  Argument errors
  *     are detected on the host before any launch and returned as negative
  *     codes; numerical trouble is never a call failure but a per-stencil status.
@@ -49,11 +51,18 @@ typedef int32_t rbf_status;
 #define RBF_EHIP         -5  /* HIP runtime error (launch or device)             */
 #define RBF_EUNSUPPORTED -6  /* n_max + m beyond the compiled system sizes       */
 
-/* operator selection (op_mask bits) */
+/* operator selection (op_mask bits); the second derivatives d2/dx_a dx_b are the
+ * building blocks of the general second-order operator of eq. (gen-op), Sec. 3.3 */
 #define RBF_OP_LAP 1u
 #define RBF_OP_DX  2u
 #define RBF_OP_DY  4u
 #define RBF_OP_DZ  8u
+#define RBF_OP_DXX 16u
+#define RBF_OP_DXY 32u
+#define RBF_OP_DXZ 64u
+#define RBF_OP_DYY 128u
+#define RBF_OP_DYZ 256u
+#define RBF_OP_DZZ 512u
 
 /* per-stencil status values (int8) */
 #define RBF_ST_OK                   0  /* FP64 solve, reproduction check passed      */
@@ -124,14 +133,16 @@ rbf_status rbf_select_stencils(rbf_ctx* ctx, const double* X, int64_t N, int d,
  * operators at p*; the system is solved (LU with partial pivoting, or FP32 LU
  * with FP64 refinement and FP64 fallback), the Lagrange multipliers are
  * discarded and the weights scaled back by s^-2 (LAP) or s^-1 (DX, DY, DZ).
- * Each stencil's weights pass an FP64 polynomial-reproduction check
- * (second block row of the system) before they are accepted.
+ * Second derivatives d2/dx_a dx_b (RBF_OP_DXX ..) use
+ * (d_ab phi_j)(0) = k r^(k-2) delta_ab + k (k-2) r^(k-4) x_a x_b and are scaled
+ * back by s^-2.  Each stencil's weights pass an FP64 polynomial-reproduction
+ * check (second block row of the system) before they are accepted.
  *
  * degree: uniform augmentation degree (0..4).  n_max bounds every n_i; the
  * system size n_max + m must be <= 128.  Systems above 64 unknowns are solved
  * in float64 (LU, two rows per lane) also when F32_IR is asked for, and then
  * report RBF_ST_FALLBACK.  status[N] (int8, may be NULL for F64) receives
- * RBF_ST_*.  w: [popcount(op_mask)][nnz] float64.  DZ requires d = 3.
+ * RBF_ST_*.  w: [popcount(op_mask)][nnz] float64, popcount(op_mask) <= 4.
  * No workspace is needed.
  * ------------------------------------------------------------------------ */
 rbf_status rbf_compute_weights(rbf_ctx* ctx, const double* X, int64_t N, int d,
@@ -239,6 +250,19 @@ rbf_status rbf_get_plan(const rbf_ctx* ctx, rbf_plan* plan);
 rbf_status rbf_apply_operators(rbf_ctx* ctx, int64_t N, const int64_t* offsets,
                                const int32_t* idx, const double* w, int n_ops, int64_t nnz,
                                int n_max, const double* u, int64_t n_u, double* out);
+
+/* ------------------------------------------------------------------------ *
+ * General second-order operator from stored weights, eq. (gen-op), Sec. 3.3:
+ * for L = sum_alpha a_alpha(p) d^alpha,
+ *   out[p] = sum_{k < n_ops} coef[i * n_ops + k] * w[k * nnz + p]
+ * for every position p of row i (w: n_ops stored operator rows, e.g. DX, DY,
+ * DXX, DXY, DYY; coef[N][n_ops] the coefficients a_alpha at the nodes).
+ * n_ops in 1..10; out[nnz] may not alias w.  n_max only chooses the lanes per
+ * row.  Rows whose range lies outside [0, nnz] are left unwritten.
+ * ------------------------------------------------------------------------ */
+rbf_status rbf_combine_operators(rbf_ctx* ctx, int64_t N, const int64_t* offsets, int64_t nnz,
+                                 int n_max, const double* w, int n_ops, const double* coef,
+                                 double* out);
 
 /* node kinds of the explicit step (uint8) */
 #define RBF_NODE_INTERIOR  0

@@ -8,6 +8,8 @@ Python face of the HIP library ``librbffd.so`` (C ABI in include/rbffd.h):
                      -- GWLS weights (monomial basis, Gaussian or unit weight function)
     assemble_csr     -- the sparse operator in CSR form
     apply_operators  -- explicit evaluation w^T u_{I(i)} of the operators on a field
+    combine_operators
+                     -- the general second-order operator from stored weights (eq. gen-op)
     explicit_step    -- one explicit Euler step (interior, Dirichlet and Neumann nodes)
     assemble_implicit / bicgstab
                      -- the implicit system M u = r and its BiCGStab solution on the GPU
@@ -23,7 +25,7 @@ from ._binding import (  # noqa: F401
     OPS, ST_BADSIZE, ST_FALLBACK, ST_OK, ST_REFINED, ST_SINGULAR, ST_SURROGATE, ST_SURROGATE_REJECTED,
     Context, Domain, RbfError, assemble_csr, autotune_batched, compute_weights, compute_weights_batched, context,
     get_plan, lib, select_stencils, set_plan, compute_weights_wls,
-    NODE_DIRICHLET, NODE_INTERIOR, NODE_NEUMANN, apply_operators, explicit_step,
+    NODE_DIRICHLET, NODE_INTERIOR, NODE_NEUMANN, apply_operators, combine_operators, explicit_step,
     SOLVE_BADDIAG, SOLVE_BREAKDOWN, SOLVE_CONVERGED, SOLVE_MAXITER, assemble_implicit, bicgstab, bicgstab_workspace,
     MLP_NPARAM, mlp_adam, mlp_flatten, mlp_forward, mlp_grad, mlp_pack, mlp_unflatten, surrogate_dataset,
     surrogate_load, surrogate_weights,

@@ -17,8 +17,8 @@ import torch
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "librbffd.so")
 
-OPS = ("lap", "dx", "dy", "dz")
-OP_BITS = {"lap": 1, "dx": 2, "dy": 4, "dz": 8}
+OPS = ("lap", "dx", "dy", "dz", "dxx", "dxy", "dxz", "dyy", "dyz", "dzz")
+OP_BITS = {o: 1 << i for i, o in enumerate(OPS)}
 PREC = {"f64": 0, "f32_ir": 1}
 
 ST_OK, ST_REFINED, ST_FALLBACK, ST_SURROGATE, ST_SURROGATE_REJECTED = 0, 1, 2, 3, 4
@@ -85,6 +85,7 @@ _SIGS = {
     "rbf_surrogate_weights": [_P, _P, _I64, _I, _P, _P, _I64, _I, ctypes.POINTER(rbf_options), _P, _P],
     "rbf_get_plan": [_P, ctypes.POINTER(rbf_plan)],
     "rbf_apply_operators": [_P, _I64, _P, _P, _P, _I, _I64, _I, _P, _I64, _P],
+    "rbf_combine_operators": [_P, _I64, _P, _I64, _I, _P, _I, _P, _P],
     "rbf_explicit_step": [_P, _I64, _I, _P, _P, _I64, _I, _P, _P, _P, _P, _P, _P, _P, ctypes.c_double, _P],
     "rbf_compute_weights_wls": [_P, _P, _I64, _I, _P, _P, _I64, _I, _I, _U, _I, ctypes.c_double,
                                 ctypes.POINTER(rbf_options), _P, _P],
@@ -178,6 +179,8 @@ def options(precision="f64", max_refine=10, phs_power=3, scale_mode=0, repro_tol
 def op_mask(ops) -> int:
     m = 0
     for o in ops:
+        if o not in OP_BITS:
+            raise RbfError(f"unknown operator {o!r}; known: {OPS}")
         m |= OP_BITS[o]
     return m
 
@@ -336,6 +339,24 @@ def explicit_step(offsets: torch.Tensor, idx: torch.Tensor, n_max: int, w_lap: t
                                    opt(g, "g"), opt(s, "s"), _dev(u, torch.float64, "u"), float(dt),
                                    _dev(out, torch.float64, "out")),
            "rbf_explicit_step")
+    return out
+
+
+def combine_operators(offsets: torch.Tensor, w: torch.Tensor, n_max: int, coef: torch.Tensor, out=None,
+                      ctx: Context | None = None) -> torch.Tensor:
+    """Weights of L = sum_k coef[:, k] op_k from stored operator rows w [K, nnz] (eq. gen-op)."""
+    ctx = ctx or context(offsets.device)
+    N = offsets.numel() - 1
+    K, nnz = w.shape
+    if tuple(coef.shape) != (N, K):
+        raise RbfError(f"coef must be [{N}, {K}], got {tuple(coef.shape)}")
+    out = torch.empty(nnz, dtype=torch.float64, device=offsets.device) if out is None else out
+    if out.numel() != nnz:
+        raise RbfError("out must have nnz entries")
+    _check(lib().rbf_combine_operators(ctx._sync_stream(), N, _dev(offsets, torch.int64, "offsets"), nnz,
+                                       int(n_max), _dev(w, torch.float64, "w"), K, _dev(coef, torch.float64, "coef"),
+                                       _dev(out, torch.float64, "out")),
+           "rbf_combine_operators")
     return out
 
 

@@ -128,6 +128,37 @@ __global__ __launch_bounds__(256) void k_explicit(int64_t N, int d, const int64_
     }
 }
 
+// out[p] = sum_k coef[row][k] w[k][p] over the row's range (eq. gen-op)
+template <int G, int E>
+__global__ __launch_bounds__(256) void k_combine(int64_t N, const int64_t* __restrict__ offsets, int64_t nnz,
+                                                 const double* __restrict__ w, int K,
+                                                 const double* __restrict__ coef, double* __restrict__ out) {
+    const int gl = threadIdx.x & (G - 1);
+    const int64_t row = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G;
+    if (row >= N) return;
+    const int64_t off = offsets[row], end = offsets[row + 1];
+    if (off < 0 || end < off || end > nnz) return;
+    double c[10];
+#pragma unroll
+    for (int k = 0; k < 10; ++k) c[k] = (k < K) ? coef[row * K + k] : 0.0;
+    for (int64_t e = gl; e < end - off; e += G) {
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < 10; ++k)
+            if (k < K) v = fma(c[k], w[(int64_t)k * nnz + off + e], v);
+        out[off + e] = v;
+    }
+}
+
+template <int G, int E>
+struct CombineL {
+    static hipError_t launch(dim3 grid, hipStream_t s, int64_t N, const int64_t* offsets, int64_t nnz,
+                             const double* w, int K, const double* coef, double* out) {
+        hipLaunchKernelGGL((k_combine<G, E>), grid, dim3(256), 0, s, N, offsets, nnz, w, K, coef, out);
+        return hipGetLastError();
+    }
+};
+
 template <int R>
 struct ApplyL {
     template <int G, int E>
@@ -191,5 +222,16 @@ extern "C" rbf_status rbf_explicit_step(rbf_ctx* ctx, int64_t N, int d, const in
     RBF_HIP_CHECK(hipSetDevice(ctx->device));
     const hipError_t e = dispatch_row_shape<ExplicitL>(n_max, N, ctx->stream, N, d, offsets, idx, nnz, w_lap, w_grad,
                                                    kind, normals, g, s, u, dt, u_new);
+    return e == hipSuccess ? RBF_OK : RBF_EHIP;
+}
+
+extern "C" rbf_status rbf_combine_operators(rbf_ctx* ctx, int64_t N, const int64_t* offsets, int64_t nnz, int n_max,
+                                            const double* w, int n_ops, const double* coef, double* out) {
+    if (!ctx || !offsets || !w || !coef || !out || N < 1 || nnz < 0 || n_max < 1) return RBF_EINVAL;
+    if (n_ops < 1 || n_ops > 10) return RBF_EINVAL;
+    if (ranges_overlap(out, (size_t)nnz * sizeof(double), w, (size_t)n_ops * (size_t)nnz * sizeof(double)))
+        return RBF_EINVAL;
+    RBF_HIP_CHECK(hipSetDevice(ctx->device));
+    const hipError_t e = dispatch_row_shape<CombineL>(n_max, N, ctx->stream, N, offsets, nnz, w, n_ops, coef, out);
     return e == hipSuccess ? RBF_OK : RBF_EHIP;
 }

@@ -122,7 +122,8 @@ rbf_status check_doms(const rbf_domain_desc* doms, int n_doms, int64_t* total) {
         const rbf_domain_desc& D = doms[k];
         if (!D.X || !D.offsets || !D.idx || !D.w || !D.status || D.N < 1 || D.nnz < 1 || D.n_max < 1) return RBF_EINVAL;
         if (D.d != 2 && D.d != 3) return RBF_EDIM;
-        if (D.op_mask == 0 || (D.op_mask & ~0xFu) || (D.d == 2 && (D.op_mask & RBF_OP_DZ))) return RBF_EINVAL;
+        unsigned opc;
+        if (op_slots(D.op_mask, D.d, &opc) < 0) return RBF_EINVAL;
         if (!D.degree && (D.degree_uniform < 0 || D.degree_uniform > 4)) return RBF_EUNSUPPORTED;
         if (D.n_max > D.N) return RBF_ETOOFEW;
         t += D.N;
@@ -154,7 +155,10 @@ rbf_status run_batched(rbf_ctx* ctx, const rbf_domain_desc* doms, int n_doms, co
         B.a.idx = D.idx;
         B.a.nnz = D.nnz;
         B.a.n_max = D.n_max;
-        B.a.op_mask = D.op_mask;
+        unsigned opc = 0;
+        const int R = op_slots(D.op_mask, D.d, &opc);  // validated by check_doms
+        B.a.op_mask = (1u << R) - 1u;
+        B.a.opc = opc;
         B.a.phs_power = o.phs_power;
         B.a.scale_mode = o.scale_mode;
         B.a.repro_tol = o.repro_tol;

@@ -71,6 +71,7 @@ __device__ __forceinline__ StencilArgs uniform_args(const StencilArgs& a0) {
     a.nnz = rfl64(a0.nnz);
     a.n_max = rfl(a0.n_max);
     a.op_mask = (unsigned)rfl((int)a0.op_mask);
+    a.opc = (unsigned)rfl((int)a0.opc);
     a.phs_power = rfl(a0.phs_power);
     a.scale_mode = rfl(a0.scale_mode);
     a.repro_tol = rfld(a0.repro_tol);

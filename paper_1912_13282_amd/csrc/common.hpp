@@ -45,6 +45,25 @@ __host__ __device__ constexpr int binom(int n, int k) {
 // number of monomials of total degree <= P in D variables
 __host__ __device__ constexpr int n_mono(int D, int P) { return binom(P + D, D); }
 
+// The operators selected in op_mask (the RBF_OP_* bits, LAP .. DZZ) fill the
+// right-hand-side slots 0..R-1 in bit order; *opc receives one 4-bit code per
+// slot (the operator's bit index).  Returns R, or -1 for an empty mask, an
+// unknown bit, more than four operators, or an operator along z in 2D.
+inline int op_slots(unsigned op_mask, int d, unsigned* opc) {
+    const unsigned zops = RBF_OP_DZ | RBF_OP_DXZ | RBF_OP_DYZ | RBF_OP_DZZ;
+    if (op_mask == 0 || (op_mask & ~0x3FFu) || (d == 2 && (op_mask & zops))) return -1;
+    unsigned c = 0;
+    int R = 0;
+    for (int b = 0; b < 10; ++b) {
+        if (!(op_mask & (1u << b))) continue;
+        if (R == 4) return -1;
+        c |= (unsigned)b << (4 * R);
+        ++R;
+    }
+    *opc = c;
+    return R;
+}
+
 // ---------------------------------------------------------------- device side
 __device__ __forceinline__ int lane_id() { return __lane_id(); }
 

@@ -46,7 +46,9 @@ extern "C" rbf_status rbf_compute_weights(rbf_ctx* ctx, const double* X, int64_t
                                           const rbf_options* opt, double* w, int8_t* status) {
     if (!ctx || !X || !offsets || !idx || !w || N < 1 || nnz < 1) return RBF_EINVAL;
     if (d != 2 && d != 3) return RBF_EDIM;
-    if (op_mask == 0 || (op_mask & ~0xFu) || (d == 2 && (op_mask & RBF_OP_DZ))) return RBF_EINVAL;
+    unsigned opc;
+    const int R = op_slots(op_mask, d, &opc);
+    if (R < 0) return RBF_EINVAL;
     if (degree < 0 || degree > 4 || n_max < 1) return RBF_EINVAL;
     if (n_max > N) return RBF_ETOOFEW;
     rbf_options o;
@@ -71,7 +73,8 @@ extern "C" rbf_status rbf_compute_weights(rbf_ctx* ctx, const double* X, int64_t
     a.idx = idx;
     a.nnz = nnz;
     a.n_max = n_max;
-    a.op_mask = op_mask;
+    a.op_mask = (1u << R) - 1u;
+    a.opc = opc;
     a.phs_power = o.phs_power;
     a.scale_mode = o.scale_mode;
     a.repro_tol = o.repro_tol;

@@ -33,7 +33,7 @@ __device__ __forceinline__ bool wls_repro(const StencilArgs& a, int n, int m, co
         const double ab = wave_sum_dpp_d(fabs(v));
         if (!(a.op_mask & (1u << q))) continue;
         double lp = 0.0;
-        for (int l = 0; l < m; ++l) lp += check_coef(l) * mono_lq(a.d, l, q);
+        for (int l = 0; l < m; ++l) lp += check_coef(l) * mono_lop(a.d, l, slot_op(a.opc, q));
         // multiplicative form: weights that are exactly zero (a Laplacian of degree <= 1) pass
         ok = ok && (fabs(s - lp) <= a.repro_tol * (ab + fabs(lp)));
     }
@@ -120,7 +120,7 @@ __device__ __forceinline__ void stencil_wls(const StencilArgs& a, int64_t node, 
             for (int q = 0; q < NR; ++q) {
                 if (!(a.op_mask & (1u << q))) continue;
                 const double acc = wave_sum_dpp_d(lane < k ? A[k] * zl[q] : 0.0);  // sum_{i<k} R_ik z_i
-                const double zk = (mono_lq(a.d, k, q) - acc) / rk;
+                const double zk = (mono_lop(a.d, k, slot_op(a.opc, q)) - acc) / rk;
                 if (lane == k) zl[q] = zk;
             }
         }
@@ -164,7 +164,9 @@ extern "C" rbf_status rbf_compute_weights_wls(rbf_ctx* ctx, const double* X, int
                                               const rbf_options* opt, double* w, int8_t* status) {
     if (!ctx || !X || !offsets || !idx || !w || N < 1 || nnz < 1) return RBF_EINVAL;
     if (d != 2 && d != 3) return RBF_EDIM;
-    if (op_mask == 0 || (op_mask & ~0xFu) || (d == 2 && (op_mask & RBF_OP_DZ))) return RBF_EINVAL;
+    unsigned opc;
+    const int R = op_slots(op_mask, d, &opc);
+    if (R < 0) return RBF_EINVAL;
     if (degree < 0 || degree > 4 || n_max < 1) return RBF_EINVAL;
     if (n_max > N) return RBF_ETOOFEW;
     if (n_max > WAVE) return RBF_EUNSUPPORTED;
@@ -184,7 +186,8 @@ extern "C" rbf_status rbf_compute_weights_wls(rbf_ctx* ctx, const double* X, int
     a.idx = idx;
     a.nnz = nnz;
     a.n_max = n_max;
-    a.op_mask = op_mask;
+    a.op_mask = (1u << R) - 1u;
+    a.opc = opc;
     a.phs_power = 3;  // unused by this engine
     a.scale_mode = o.scale_mode;
     a.repro_tol = o.repro_tol;

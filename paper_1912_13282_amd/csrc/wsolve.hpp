@@ -28,7 +28,7 @@
 
 namespace rbf {
 
-constexpr int NR = 4;  // right-hand sides: Laplacian, d/dx, d/dy, d/dz (d/dz unused in 2D)
+constexpr int NR = 4;  // right-hand-side slots; each holds one operator (StencilArgs::opc)
 
 // Monomial exponents of total degree <= 4 in graded order (degree ascending,
 // then x-power descending, then y-power descending); the first C(P+d, d)
@@ -90,6 +90,88 @@ __device__ __forceinline__ double mono_lq(int d, int l, int op) {
     return (op - 1 < d && s == 1 && e[op - 1] == 1) ? 1.0 : 0.0;
 }
 
+// Operator codes of the right-hand-side slots (one 4-bit code per slot in
+// StencilArgs::opc, the bit index of the operator in rbffd.h): 0 Laplacian,
+// 1..3 d/dx_a, 4..9 the second derivatives xx, xy, xz, yy, yz, zz.
+__host__ __device__ constexpr int op_order(int code) { return (code >= 1 && code <= 3) ? 1 : 2; }
+__device__ __forceinline__ int slot_op(unsigned opc, int q) { return (int)((opc >> (4 * q)) & 15u); }
+__device__ __forceinline__ void op_axes(int code, int& ax, int& bx) {
+    switch (code) {
+        case 4: ax = 0; bx = 0; break;
+        case 5: ax = 0; bx = 1; break;
+        case 6: ax = 0; bx = 2; break;
+        case 7: ax = 1; bx = 1; break;
+        case 8: ax = 1; bx = 2; break;
+        default: ax = 2; bx = 2; break;
+    }
+}
+
+// (L q_l)(0) for every operator code, dimension and monomial, tabulated at
+// compile time (a table lookup keeps the solvers' registers free): Laplacian 2
+// for x_a^2; d_a 1 for x_a; d_ab 1 for x_a x_b (a != b), 2 for x_a^2 (a = b).
+struct MonoOpTable {
+    double v[10][2][35];
+    constexpr MonoOpTable() : v() {
+        constexpr int A[6] = {0, 0, 0, 1, 1, 2}, B[6] = {0, 1, 2, 1, 2, 2};
+        for (int dd = 0; dd < 2; ++dd) {
+            int e[35][3] = {};
+            int c = 0;
+            for (int deg = 0; deg <= 4; ++deg) {
+                if (dd == 0) {
+                    for (int a = deg; a >= 0; --a) {
+                        e[c][0] = a;
+                        e[c][1] = deg - a;
+                        e[c][2] = 0;
+                        ++c;
+                    }
+                } else {
+                    for (int a = deg; a >= 0; --a)
+                        for (int b = deg - a; b >= 0; --b) {
+                            e[c][0] = a;
+                            e[c][1] = b;
+                            e[c][2] = deg - a - b;
+                            ++c;
+                        }
+                }
+            }
+            for (int l = 0; l < c; ++l) {
+                const int s = e[l][0] + e[l][1] + e[l][2];
+                v[0][dd][l] = (s == 2 && (e[l][0] == 2 || e[l][1] == 2 || e[l][2] == 2)) ? 2.0 : 0.0;
+                for (int a = 0; a < 3; ++a) v[1 + a][dd][l] = (a < dd + 2 && s == 1 && e[l][a] == 1) ? 1.0 : 0.0;
+                for (int k = 0; k < 6; ++k) {
+                    const int ax = A[k], bx = B[k];
+                    double t = 0.0;
+                    if (s == 2) {
+                        if (ax == bx) t = e[l][ax] == 2 ? 2.0 : 0.0;
+                        else t = (e[l][ax] == 1 && e[l][bx] == 1) ? 1.0 : 0.0;
+                    }
+                    v[4 + k][dd][l] = t;
+                }
+            }
+        }
+    }
+};
+__constant__ constexpr MonoOpTable kMonoOp{};
+
+__device__ __forceinline__ double mono_lop(int d, int l, int code) { return kMonoOp.v[code][d - 2][l]; }
+
+// (L phi_j)(0) for phi(r) = r^k about the scaled offset x = x_j, r2 = |x_j|^2,
+// pw = |x_j|^(k-2):  Laplacian k (k + d - 2) pw;  d_a: -k pw x_a;
+// d_ab: k pw delta_ab + k (k - 2) pw / r2 x_a x_b (the second term is 0 at x_j = 0).
+// Written branch-free (alpha pw + beta pw x_a + gamma x_a x_b with per-code
+// constants): with branches per code the one-row-per-lane solvers spill.
+__device__ __forceinline__ double phs_lop(int code, const double (&x)[3], double r2, double pw, int kpow, int d) {
+    const bool lap = code == 0, first = code >= 1 && code <= 3, second = code >= 4;
+    const int ia = first ? code - 1 : (code <= 6 ? 0 : (code <= 8 ? 1 : 2));
+    const int ib = (code == 4) ? 0 : (code == 5 || code == 7) ? 1 : 2;
+    const double xa = ia == 0 ? x[0] : (ia == 1 ? x[1] : x[2]);
+    const double xb = ib == 0 ? x[0] : (ib == 1 ? x[1] : x[2]);
+    const double alpha = lap ? (double)(kpow * (kpow + d - 2)) : ((second && ia == ib) ? (double)kpow : 0.0);
+    const double beta = (first && code <= d) ? -(double)kpow : 0.0;
+    const double gamma = (second && r2 > 0.0) ? (double)(kpow * (kpow - 2)) * (pw / r2) : 0.0;
+    return alpha * pw + beta * pw * xa + gamma * xa * xb;
+}
+
 // fixed coefficients of the test polynomial of the reproduction check
 __host__ __device__ constexpr double check_coef(int l) { return 1.0 + 0.6180339887498949 * ((l * 7 + 3) % 11) / 11.0; }
 
@@ -108,7 +190,8 @@ struct StencilArgs {
     const int32_t* idx;
     int64_t nnz;
     int n_max;
-    unsigned op_mask;
+    unsigned op_mask;   // active right-hand-side slots (bits 0..NR-1)
+    unsigned opc = 0x3210u;  // operator code of each slot (4 bits per slot), see slot_op
     int phs_power;
     int scale_mode;
     double repro_tol;
@@ -236,12 +319,11 @@ __device__ __forceinline__ void assemble_row(const StencilArgs& a, const FrameG<
         const double r2 = F.xh[0][0] * F.xh[0][0] + F.xh[0][1] * F.xh[0][1] + F.xh[0][2] * F.xh[0][2];
         const double rr = sqrt(r2);
         const double pw = (kpow == 5) ? r2 * rr : rr;  // ||x_j||^(k-2)
-        rhs[0] = (double)(kpow * (kpow + d - 2)) * pw;
 #pragma unroll
-        for (int q = 1; q < NR; ++q) rhs[q] = (q <= d) ? -(double)kpow * pw * F.xh[0][q - 1] : 0.0;
+        for (int q = 0; q < NR; ++q) rhs[q] = phs_lop(slot_op(a.opc, q), F.xh[0], r2, pw, kpow, d);
     } else if (r < m) {
 #pragma unroll
-        for (int q = 0; q < NR; ++q) rhs[q] = mono_lq(d, r, q);
+        for (int q = 0; q < NR; ++q) rhs[q] = mono_lop(d, r, slot_op(a.opc, q));
     }
 }
 
@@ -276,7 +358,7 @@ __device__ __forceinline__ bool repro_check(const StencilArgs& a, int n, int m, 
         const double ab = wave_sum_dpp_d(A[q]);
         if (!(a.op_mask & (1u << q))) continue;
         double lp = 0.0;
-        for (int l = 0; l < m; ++l) lp += check_coef(l) * mono_lq(d, l, q);
+        for (int l = 0; l < m; ++l) lp += check_coef(l) * mono_lop(d, l, slot_op(a.opc, q));
         ok = ok && (fabs(s - lp) / (ab + fabs(lp)) <= a.repro_tol);
     }
     return ok;
@@ -292,7 +374,7 @@ __device__ __forceinline__ void store_weights(const StencilArgs& a, int64_t node
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
         if (!(a.op_mask & (1u << q))) continue;
-        const double sc = (q == 0) ? sc2 : F.inv_s;
+        const double sc = op_order(slot_op(a.opc, q)) == 2 ? sc2 : F.inv_s;
 #pragma unroll
         for (int t = 0; t < RPL; ++t) {
             const int j = lane + 64 * t - m;
@@ -475,12 +557,11 @@ __device__ __forceinline__ void rhs_row(const StencilArgs& a, const FrameG<1>& F
         const double r2 = F.xh[0][0] * F.xh[0][0] + F.xh[0][1] * F.xh[0][1] + F.xh[0][2] * F.xh[0][2];
         const double rr = sqrt(r2);
         const double pw = (kpow == 5) ? r2 * rr : rr;  // ||x_j||^(k-2)
-        rhs[0] = (double)(kpow * (kpow + d - 2)) * pw;
 #pragma unroll
-        for (int q = 1; q < NR; ++q) rhs[q] = (q <= d) ? -(double)kpow * pw * F.xh[0][q - 1] : 0.0;
+        for (int q = 0; q < NR; ++q) rhs[q] = phs_lop(slot_op(a.opc, q), F.xh[0], r2, pw, kpow, d);
     } else if (r < m) {
 #pragma unroll
-        for (int q = 0; q < NR; ++q) rhs[q] = mono_lq(d, r, q);
+        for (int q = 0; q < NR; ++q) rhs[q] = mono_lop(d, r, slot_op(a.opc, q));
     }
 }
 

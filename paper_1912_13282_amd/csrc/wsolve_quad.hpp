@@ -219,12 +219,11 @@ __device__ __forceinline__ void stencil_f64_quad(const StencilArgs& a, int64_t n
             const double rr2 = xr[0] * xr[0] + xr[1] * xr[1] + xr[2] * xr[2];
             const double rr = sqrt(rr2);
             const double pw = (kpow == 5) ? rr2 * rr : rr;  // ||x_j||^(k-2)
-            rhs[0] = (double)(kpow * (kpow + d - 2)) * pw;
 #pragma unroll
-            for (int q = 1; q < NR; ++q) rhs[q] = (q <= d) ? -(double)kpow * pw * xr[q - 1] : 0.0;
+            for (int q = 0; q < NR; ++q) rhs[q] = phs_lop(slot_op(a.opc, q), xr, rr2, pw, kpow, d);
         } else if (r < m) {
 #pragma unroll
-            for (int q = 0; q < NR; ++q) rhs[q] = mono_lq(d, r, q);
+            for (int q = 0; q < NR; ++q) rhs[q] = mono_lop(d, r, slot_op(a.opc, q));
         }
     }
 
@@ -274,7 +273,7 @@ __device__ __forceinline__ void stencil_f64_quad(const StencilArgs& a, int64_t n
         const double sq = (red[2 * q] + red[8 + 2 * q]) + (red[16 + 2 * q] + red[24 + 2 * q]);
         const double aq = (red[2 * q + 1] + red[8 + 2 * q + 1]) + (red[16 + 2 * q + 1] + red[24 + 2 * q + 1]);
         double lp = 0.0;
-        for (int l2 = 0; l2 < m; ++l2) lp += check_coef(l2) * mono_lq(d, l2, q);
+        for (int l2 = 0; l2 < m; ++l2) lp += check_coef(l2) * mono_lop(d, l2, slot_op(a.opc, q));
         good = good && (fabs(sq - lp) / (aq + fabs(lp)) <= a.repro_tol);
     }
     if (tid < n) {
@@ -282,7 +281,7 @@ __device__ __forceinline__ void stencil_f64_quad(const StencilArgs& a, int64_t n
 #pragma unroll
         for (int q = 0; q < NR; ++q) {
             if (!(a.op_mask & (1u << q))) continue;
-            const double sc = (q == 0) ? inv_s * inv_s : inv_s;
+            const double sc = op_order(slot_op(a.opc, q)) == 2 ? inv_s * inv_s : inv_s;
             a.w[ro * a.nnz + off + tid] = good ? w4[q] * sc : __builtin_nan("");
             ++ro;
         }
