@@ -78,12 +78,19 @@ __device__ __forceinline__ void quad_eliminate(double (&row)[H], double (&rhs)[N
                 piv = true;
                 mystep = k;
                 invd = inv;
+                // one 8-byte store per value, kept apart by an empty asm: merged stores
+                // need their data in an aligned register tuple (a copy of every value)
 #pragma unroll
-                for (int cl = 0; cl < H; ++cl)
+                for (int cl = 0; cl < H; ++cl) {
                     if (H * CH + cl > k) prow[H * CH + cl] = row[cl];
+                    asm volatile("" ::: "memory");
+                }
                 if (CH == 0)
 #pragma unroll
-                    for (int q = 0; q < NR; ++q) prow[M2 + q] = rhs[q];
+                    for (int q = 0; q < NR; ++q) {
+                        prow[M2 + q] = rhs[q];
+                        asm volatile("" ::: "memory");
+                    }
             }
             __syncthreads();
 #pragma unroll
