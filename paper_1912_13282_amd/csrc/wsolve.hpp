@@ -435,18 +435,18 @@ __device__ __forceinline__ bool gauss_jordan(T (&row)[MAXM], T (&rhs)[NR], T* pr
         if (me) {
             piv = true;
             mystep = k;
-            // float64: one 8-byte store per value, kept apart by an empty asm (merged
-            // stores need their data in an aligned register tuple, which costs a copy
-            // of every value); the reads below stay 16-byte
+            // one store per value, kept apart by an empty asm (merged stores need their
+            // data in an aligned register tuple, which costs a copy of every value);
+            // the reads below stay 16-byte
 #pragma unroll
             for (int j = k; j < MAXM; ++j) {
                 if (!GUARD || j < M) buf[j] = row[j];
-                if constexpr (sizeof(T) == 8) asm volatile("" ::: "memory");
+                asm volatile("" ::: "memory");
             }
 #pragma unroll
             for (int q = 0; q < NR; ++q) {
                 buf[RO + q] = rhs[q];
-                if constexpr (sizeof(T) == 8) asm volatile("" ::: "memory");
+                asm volatile("" ::: "memory");
             }
         }
         wave_lds_sync();
