@@ -418,14 +418,15 @@ __device__ __forceinline__ bool gauss_jordan(T (&row)[MAXM], T (&rhs)[NR], T* pr
     int mystep = -1;
     T invd = (T)0;
     int pmin = 0x7F7FFFFF, pmax = 0;  // bit patterns of the smallest / largest pivot magnitude
+    // Pivot search on float magnitudes (partial pivoting needs a large pivot, not
+    // the exact maximum), compared as bit patterns (a NaN wins and marks the system
+    // bad); the first lane with the maximum wins.  The search of step k + 1 runs as
+    // soon as column k + 1 is updated, overlapping the rest of step k's update.
+    int cand = piv ? -1 : __float_as_int((float)fabs(row[0]));
+    int mi = wave_max_dpp_i(cand);
 #pragma unroll
     for (int k = 0; k < MAXM; ++k) {
         if (GUARD && k >= M) continue;
-        // pivot search on float magnitudes (partial pivoting needs a large pivot,
-        // not the exact maximum), compared as bit patterns (a NaN wins and marks
-        // the system bad); the first lane with the maximum wins
-        const int cand = piv ? -1 : __float_as_int((float)fabs(row[k]));
-        const int mi = wave_max_dpp_i(cand);
         pmin = min(pmin, mi);  // a zero pivot: singular
         pmax = max(pmax, mi);  // an infinite or NaN pivot
         const uint64_t b = ballot64(!piv && cand == mi);
@@ -454,6 +455,7 @@ __device__ __forceinline__ bool gauss_jordan(T (&row)[MAXM], T (&rhs)[NR], T* pr
         if (me) invd = inv;
         const T l = me ? (T)0 : row[k] * inv;
         if (keep_multipliers && !me) row[k] = l;
+        const bool next = k + 1 < MAXM && (!GUARD || k + 1 < M);
 #pragma unroll
         for (int j0 = ((k + 1) / V) * V; j0 < MAXM; j0 += V) {
             if (GUARD && j0 >= M) continue;
@@ -462,6 +464,10 @@ __device__ __forceinline__ bool gauss_jordan(T (&row)[MAXM], T (&rhs)[NR], T* pr
 #pragma unroll
             for (int e = 0; e < V; ++e)
                 if (j0 + e > k && j0 + e < MAXM && (!GUARD || j0 + e < M)) row[j0 + e] = fma(-l, u[e], row[j0 + e]);
+            if (j0 == ((k + 1) / V) * V && next) {  // column k + 1 is done: search step k + 1
+                cand = piv ? -1 : __float_as_int((float)fabs(row[k + 1]));
+                mi = wave_max_dpp_i(cand);
+            }
         }
         const V2 r0 = *reinterpret_cast<const V2*>(buf + RO);
         const T* u0 = reinterpret_cast<const T*>(&r0);
