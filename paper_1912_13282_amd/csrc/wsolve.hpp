@@ -594,7 +594,6 @@ __device__ __forceinline__ void stencil_ir_rows(const StencilArgs& a, int64_t no
     FrameG<1> F;
     if (!stencil_prologue<1>(a, node, P, MAXM, off, n, m, F)) return;
     const int M = n + m;
-    const int d = a.d;
     const int QW = MAXM - m;
     double* qt = lds + L::o_qt;
     double* xh = lds + L::o_xh;
@@ -677,7 +676,7 @@ __device__ __forceinline__ void stencil_ir_rows(const StencilArgs& a, int64_t no
                 bool conv = true;
 #pragma unroll
                 for (int q = 0; q < NR; ++q) {
-                    if (q > d) continue;  // the d/dz column is empty in 2D
+                    if (!(a.op_mask & (1u << q))) continue;  // slots without an operator
                     const double rn = wave_max_dpp_d(live ? fabs(r[q]) : 0.0);
                     const double xn = wave_max_dpp_d(live ? fabs(x[q]) : 0.0);
                     conv = conv && (rn <= tolc * knorm * xn);

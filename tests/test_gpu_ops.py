@@ -40,6 +40,9 @@ def _t(a, dev):
 CASES = {  # name: (node set, n, degree, ops)
     "disk_hessian": (lambda: ns.disk(0.05, 61), 15, 2, ("dxx", "dxy", "dyy")),
     "disk_mixed": (lambda: ns.disk(0.05, 62), 20, 3, ("lap", "dy", "dxy")),
+    # four operators in 2D: a second derivative in the last slot, whose refinement
+    # must be checked like the others
+    "disk_four": (lambda: ns.disk(0.05, 71), 20, 3, ("lap", "dx", "dy", "dxx")),
     "cube_hessian_a": (lambda: ns.cube_minus_sphere(1.0 / 12, 63), 35, 3, ("dxx", "dxy", "dxz", "dyy")),
     "cube_hessian_b": (lambda: ns.cube_minus_sphere(1.0 / 12, 63), 35, 3, ("dz", "dyz", "dzz")),
     "cube_large": (lambda: ns.cube_minus_sphere(1.0 / 10, 64), 65, 4, ("dxy", "dzz")),   # n + m = 100
