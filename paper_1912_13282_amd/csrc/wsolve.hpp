@@ -175,9 +175,25 @@ __device__ __forceinline__ double phs_lop(int code, const double (&x)[3], double
 // fixed coefficients of the test polynomial of the reproduction check
 __host__ __device__ constexpr double check_coef(int l) { return 1.0 + 0.6180339887498949 * ((l * 7 + 3) % 11) / 11.0; }
 
+// Square root of a finite x >= 0 (squared scaled offsets): the hardware
+// reciprocal square-root estimate, one Goldschmidt iteration on the coupled pair
+// g ~ sqrt(x), h ~ 1 / (2 sqrt(x)), and a final Newton correction
+// g += (x - g^2) h (Markstein), which leaves g within about an ulp of the rounded
+// square root; x = 0 gives 0.  A third of the correctly rounded sequence, whose
+// extra work scales denormal and huge arguments; one is evaluated per matrix entry.
+__device__ __forceinline__ double sqrt_basis(double x) {
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double r = fma(-g, h, 0.5);
+    g = fma(g, r, g);
+    h = fma(h, r, h);
+    g = fma(fma(-g, g, x), h, g);
+    return x > 0.0 ? g : 0.0;
+}
+
 // phi(r) = r^k for odd k in {3, 5}, from r^2
 __device__ __forceinline__ double phs_from_r2(double r2, int k) {
-    const double r = sqrt(r2);
+    const double r = sqrt_basis(r2);
     return (k == 5) ? r2 * r2 * r : r2 * r;
 }
 
@@ -459,7 +475,11 @@ __device__ __forceinline__ bool gauss_jordan(T (&row)[MAXM], T (&rhs)[NR], T* pr
 #pragma unroll
         for (int j0 = ((k + 1) / V) * V; j0 < MAXM; j0 += V) {
             if (GUARD && j0 >= M) continue;
-            const V2 uv = *reinterpret_cast<const V2*>(buf + j0);
+            typedef T VX __attribute__((ext_vector_type(V)));
+            VX uv = *reinterpret_cast<const VX*>(buf + j0);
+            // columns <= k of the first chunk are not used; without this the read is
+            // narrowed and the reads after it are re-paired off the 16-byte grid
+            asm("" : "+v"(uv));
             const T* u = reinterpret_cast<const T*>(&uv);
 #pragma unroll
             for (int e = 0; e < V; ++e)
