@@ -275,12 +275,9 @@ struct RowLds {
     static constexpr int QTE = QT + (QT & 1);
     static constexpr int XH = MAXM * 4;                  // scaled offsets, padded to 4 doubles
     static constexpr int SOL = MAXM * NR;                // solution permuted to unknown order
-    static constexpr int PRW = ((MAXM + NR + 1) / 2) * 2 + 2;   // one FP64 pivot row + RHS
-    static constexpr int PRWF = ((MAXM + NR + 3) / 4) * 4 + 4;  // one FP32 pivot row + RHS
-    static constexpr int F32 = (2 * PRWF + MAXM * NR + 1) / 2;  // FP32 rows + solution (doubles)
-    static constexpr int TOTAL = QTE + XH + SOL + 2 * PRW + F32;
-    static constexpr int o_qt = 0, o_xh = QTE, o_sol = QTE + XH, o_prow = QTE + XH + SOL,
-                         o_f32 = QTE + XH + SOL + 2 * PRW;
+    static constexpr int F32 = (MAXM * NR + 1) / 2;      // FP32 solution (in doubles)
+    static constexpr int TOTAL = QTE + XH + SOL + F32;
+    static constexpr int o_qt = 0, o_xh = QTE, o_sol = QTE + XH, o_f32 = QTE + XH + SOL;
 };
 
 // Assembly of this lane's row of K' (entries computed in float64, stored as T)
@@ -422,13 +419,13 @@ __device__ __forceinline__ float recip(float x) {
 // unknown `lane` (permuted through LDS), mystep the lane's pivot step and invd
 // 1/U_kk of that step; with keep_multipliers each row keeps its multipliers in
 // the columns it has eliminated (for gj_replay).
+//
+// The pivot row reaches the other lanes value by value through scalar
+// registers (a lane read of the pivot lane, used directly as the FMA operand):
+// no LDS store, wait and broadcast read per step.
 template <typename T, int MAXM, bool GUARD>
-__device__ __forceinline__ bool gauss_jordan(T (&row)[MAXM], T (&rhs)[NR], T* prow, T* sol_lds, T (&sol)[NR],
+__device__ __forceinline__ bool gauss_jordan(T (&row)[MAXM], T (&rhs)[NR], T* sol_lds, T (&sol)[NR],
                                              bool keep_multipliers, int& step_out, T& invd_out, int M) {
-    constexpr int V = 16 / sizeof(T);                       // values per 16-byte LDS access
-    constexpr int PRW = ((MAXM + NR + V - 1) / V) * V + V;  // one pivot row + RHS, padded
-    constexpr int RO = ((MAXM + V - 1) / V) * V;            // RHS offset inside a row buffer
-    using V2 = typename std::conditional<sizeof(T) == 8, double2, float4>::type;
     const int lane = lane_id();
     bool piv = lane >= MAXM;
     int mystep = -1;
@@ -447,61 +444,28 @@ __device__ __forceinline__ bool gauss_jordan(T (&row)[MAXM], T (&rhs)[NR], T* pr
         pmax = max(pmax, mi);  // an infinite or NaN pivot
         const uint64_t b = ballot64(!piv && cand == mi);
         const int p = first_lane(b);
-        T* buf = prow + (k & 1) * PRW;
         const bool me = (lane == p);
         if (me) {
             piv = true;
             mystep = k;
-            // one store per value, kept apart by an empty asm (merged stores need their
-            // data in an aligned register tuple, which costs a copy of every value);
-            // the reads below stay 16-byte
-#pragma unroll
-            for (int j = k; j < MAXM; ++j) {
-                if (!GUARD || j < M) buf[j] = row[j];
-                asm volatile("" ::: "memory");
-            }
-#pragma unroll
-            for (int q = 0; q < NR; ++q) {
-                buf[RO + q] = rhs[q];
-                asm volatile("" ::: "memory");
-            }
         }
-        wave_lds_sync();
-        const T inv = recip(buf[k]);
+        // values of the pivot lane are read before this step updates them (the
+        // pivot lane's own update is by a zero multiplier)
+        const T inv = recip(readlane_t<T>(row[k], p));
         if (me) invd = inv;
         const T l = me ? (T)0 : row[k] * inv;
         if (keep_multipliers && !me) row[k] = l;
-        const bool next = k + 1 < MAXM && (!GUARD || k + 1 < M);
 #pragma unroll
-        for (int j0 = ((k + 1) / V) * V; j0 < MAXM; j0 += V) {
-            if (GUARD && j0 >= M) continue;
-            typedef T VX __attribute__((ext_vector_type(V)));
-            VX uv = *reinterpret_cast<const VX*>(buf + j0);
-            // columns <= k of the first chunk are not used; without this the read is
-            // narrowed and the reads after it are re-paired off the 16-byte grid
-            asm("" : "+v"(uv));
-            const T* u = reinterpret_cast<const T*>(&uv);
-#pragma unroll
-            for (int e = 0; e < V; ++e)
-                if (j0 + e > k && j0 + e < MAXM && (!GUARD || j0 + e < M)) row[j0 + e] = fma(-l, u[e], row[j0 + e]);
-            if (j0 == ((k + 1) / V) * V && next) {  // column k + 1 is done: search step k + 1
+        for (int j = k + 1; j < MAXM; ++j) {
+            if (GUARD && j >= M) continue;
+            row[j] = fma(-l, readlane_t<T>(row[j], p), row[j]);
+            if (j == k + 1) {  // column k + 1 is done: search step k + 1
                 cand = piv ? -1 : __float_as_int((float)fabs(row[k + 1]));
                 mi = wave_max_dpp_i(cand);
             }
         }
-        const V2 r0 = *reinterpret_cast<const V2*>(buf + RO);
-        const T* u0 = reinterpret_cast<const T*>(&r0);
-        if constexpr (V == 2) {
-            const V2 r1 = *reinterpret_cast<const V2*>(buf + RO + 2);
-            const T* u1 = reinterpret_cast<const T*>(&r1);
-            rhs[0] = fma(-l, u0[0], rhs[0]);
-            rhs[1] = fma(-l, u0[1], rhs[1]);
-            rhs[2] = fma(-l, u1[0], rhs[2]);
-            rhs[3] = fma(-l, u1[1], rhs[3]);
-        } else {
 #pragma unroll
-            for (int q = 0; q < NR; ++q) rhs[q] = fma(-l, u0[q], rhs[q]);
-        }
+        for (int q = 0; q < NR; ++q) rhs[q] = fma(-l, readlane_t<T>(rhs[q], p), rhs[q]);
     }
     step_out = mystep;
     invd_out = invd;
@@ -571,8 +535,7 @@ __device__ __forceinline__ void stencil_f64_rows(const StencilArgs& a, int64_t n
     double s1[NR];
     int mystep;
     double invd;
-    const bool ok = gauss_jordan<double, MAXM, GUARD>(row, rhs, lds + L::o_prow, lds + L::o_sol, s1, false, mystep,
-                                                      invd, n + m);
+    const bool ok = gauss_jordan<double, MAXM, GUARD>(row, rhs, lds + L::o_sol, s1, false, mystep, invd, n + m);
     double sol[1][NR];
 #pragma unroll
     for (int q = 0; q < NR; ++q) sol[0][q] = ok ? s1[q] : 0.0;
@@ -618,8 +581,7 @@ __device__ __forceinline__ void stencil_ir_rows(const StencilArgs& a, int64_t no
     double* qt = lds + L::o_qt;
     double* xh = lds + L::o_xh;
     double* x64 = lds + L::o_sol;
-    float* prow = reinterpret_cast<float*>(lds + L::o_f32);
-    float* sol32 = prow + 2 * L::PRWF;
+    float* sol32 = reinterpret_cast<float*>(lds + L::o_f32);
 
     float row[MAXM];
     float b32[NR];
@@ -632,7 +594,7 @@ __device__ __forceinline__ void stencil_ir_rows(const StencilArgs& a, int64_t no
     float s32[NR];
     int mystep;
     float invd;
-    const bool ok32 = gauss_jordan<float, MAXM, GUARD>(row, b32, prow, sol32, s32, true, mystep, invd, M);
+    const bool ok32 = gauss_jordan<float, MAXM, GUARD>(row, b32, sol32, s32, true, mystep, invd, M);
     // the float64 right-hand side again (cheaper than keeping it live through the elimination)
     double B[NR];
     rhs_row(a, F, n, m, B);
