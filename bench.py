@@ -131,7 +131,8 @@ def parse():
     ap.add_argument("--form", default="f32_ir", choices=["f32_ir", "f64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="time only the reported form")
-    ap.add_argument("--cpu-sample", type=int, default=30000)
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="nodes in the CPU oracle sample (default: about 10 s of oracle work per workload)")
     ap.add_argument("--per-domain", type=int, default=2_000_000, help="mixed: nodes per domain")
     ap.add_argument("--tune-per-domain", type=int, default=200_000, help="mixed: nodes per domain of the tuning batch")
     ap.add_argument("--train-sets", type=int, default=5000, help="learned: training node sets (2,008 nodes each)")
@@ -271,7 +272,7 @@ def bench_uniform(a, torch, rb, B, name):
     vals = torch.empty((R, nnz), dtype=torch.float64, device=dev)
     ctx = rb.context(dev)
     timer = Timer(torch, ["select_stencils", "compute_weights", "assemble_csr"])
-    sample = draw_sample(N, a.cpu_sample)
+    sample = draw_sample(N, a.cpu_sample or 150_000)
     pos_t = torch.from_numpy(sample_positions(off, sample)).to(dev)
 
     def make_step(form):
@@ -404,7 +405,7 @@ def bench_mixed(a, torch, rb, B):
                 e[3].record(timer.stream)
         return step
 
-    per = max(1, a.cpu_sample // len(meta))
+    per = max(1, (a.cpu_sample or 30_000) // len(meta))
     samples = [draw_sample(mt["nd"].N, per, seed=12345 + k) for k, mt in enumerate(meta)]
     spos = [torch.from_numpy(sample_positions(mt["off"], smp)).to(dev) for mt, smp in zip(meta, samples)]
     results, snap = {}, {}
@@ -557,7 +558,7 @@ def bench_learned(a, torch, rb, B):
     if "f64" in results:
         out["learned_vs_f64"] = main["stencils_per_s"] / results["f64"]["stencils_per_s"]
     if not a.no_cpu:
-        base, soff, sidx, Wo = cpu_oracle(nd.X, 15, 2, ("lap",), draw_sample(N, a.cpu_sample))
+        base, soff, sidx, Wo = cpu_oracle(nd.X, 15, 2, ("lap",), draw_sample(N, a.cpu_sample or 30_000))
         out["cpu_baseline"] = base
     return out
 
@@ -629,7 +630,7 @@ def bench_wls(a, torch, rb, B):
 
         from oracle import knn as oknn
         from oracle import wls as owls
-        sample = draw_sample(N, a.cpu_sample)
+        sample = draw_sample(N, a.cpu_sample or 60_000)
         snap = w[:, torch.from_numpy(sample_positions(off_h, sample)).to(dev)].cpu().numpy()
         with threadpool_limits(limits=1):
             t = time.perf_counter()
