@@ -16,7 +16,8 @@
 //   * FP64: Gauss-Jordan with partial pivoting (the paper's LU continued
 //     upwards, which costs nothing extra when every lane holds one row and
 //     leaves no back substitution).  Per step the pivot search is a DPP max on
-//     float magnitudes and the pivot row goes through LDS as broadcast reads.
+//     float magnitudes and the pivot row reaches the other lanes by lane reads
+//     into scalar registers.
 //   * FP32 + FP64 refinement: float32 Gauss-Jordan that keeps each row's
 //     multipliers in its eliminated columns; corrections replay the recorded
 //     row operations on the float64 residual (K recomputed in float64 from the
