@@ -238,13 +238,33 @@ __device__ __forceinline__ bool kless(double k1, unsigned i1, double k2, unsigne
     return (k1 < k2) || (k1 == k2 && i1 < i2);
 }
 
+// value of lane ^ j.  j = 1, 2, 8 are single DPP moves (quad permutations, row
+// rotation by 8), j = 4 two of them (lane ^ 3 inside the quad, then the
+// half-row mirror, lane ^ 7); j = 16, 32 cross rows and go through the LDS
+// permute.  Every lane of the wave must be active.
+__device__ __forceinline__ int xor_lane(int v, int j) {
+    switch (j) {
+        case 1: return __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);
+        case 2: return __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);
+        case 4: {
+            const int a = __builtin_amdgcn_update_dpp(v, v, 0x1B, 0xF, 0xF, false);
+            return __builtin_amdgcn_update_dpp(a, a, 0x141, 0xF, 0xF, false);
+        }
+        case 8: return __builtin_amdgcn_update_dpp(v, v, 0x128, 0xF, 0xF, false);
+        default: return __shfl_xor(v, j);
+    }
+}
+__device__ __forceinline__ double xor_lane(double v, int j) {
+    return __hiloint2double(xor_lane(__double2hiint(v), j), xor_lane(__double2loint(v), j));
+}
+
 // compare-exchange of element e (= lane + 64 t) with e ^ j; want_min decided per element
 template <int T>
 __device__ __forceinline__ void cmpx_lane(double (&K)[T], unsigned (&I)[T], int j, const bool (&want_min)[T]) {
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-        double pk = __shfl_xor(K[t], j);
-        unsigned pi = (unsigned)__shfl_xor((int)I[t], j);
+        double pk = xor_lane(K[t], j);
+        unsigned pi = (unsigned)xor_lane((int)I[t], j);
         bool pl = kless(pk, pi, K[t], I[t]);
         bool ml = kless(K[t], I[t], pk, pi);
         bool take = want_min[t] ? pl : ml;
