@@ -138,16 +138,21 @@ rbf_status rbf_select_stencils(rbf_ctx* ctx, const double* X, int64_t N, int d,
  * back by s^-2.  Each stencil's weights pass an FP64 polynomial-reproduction
  * check (second block row of the system) before they are accepted.
  *
- * degree: uniform augmentation degree (0..4).  n_max bounds every n_i; the
- * system size n_max + m must be <= 128.  Systems above 64 unknowns are solved
- * in float64 (LU, two rows per lane) also when F32_IR is asked for, and then
- * report RBF_ST_FALLBACK.  status[N] (int8, may be NULL for F64) receives
+ * Augmentation degree (Sec. 3.2 takes it as a parameter of the approximation;
+ * Sec. 3.1 allows stencils of varying size): degree[N] (int8, device) gives
+ * each node its own degree, and degree_max (0..4) bounds them -- a node whose
+ * degree lies outside [0, degree_max] gets RBF_ST_BADSIZE; with degree == NULL
+ * every node takes degree_max.  n_max bounds every n_i; the system size
+ * n_max + C(degree_max + d, d) must be <= 128, and selects the compiled size
+ * class every stencil of the call runs in.  Systems above 64 unknowns are
+ * solved in float64 (LU, two rows per lane) also when F32_IR is asked for, and
+ * then report RBF_ST_FALLBACK.  status[N] (int8, may be NULL for F64) receives
  * RBF_ST_*.  w: [popcount(op_mask)][nnz] float64, popcount(op_mask) <= 4.
  * No workspace is needed.
  * ------------------------------------------------------------------------ */
 rbf_status rbf_compute_weights(rbf_ctx* ctx, const double* X, int64_t N, int d,
                                const int64_t* offsets, const int32_t* idx, int64_t nnz,
-                               int n_max, int degree, unsigned op_mask,
+                               int n_max, const int8_t* degree, int degree_max, unsigned op_mask,
                                const rbf_options* opt, double* w, int8_t* status);
 
 /* weight functions of the GWLS engine */

@@ -68,7 +68,7 @@ _SIGS = {
     "rbf_ctx_destroy": [_P],
     "rbf_select_stencils_workspace": [_I64, _I, _I, ctypes.POINTER(_SZ)],
     "rbf_select_stencils": [_P, _P, _I64, _I, _P, _I, _P, _P, _SZ],
-    "rbf_compute_weights": [_P, _P, _I64, _I, _P, _P, _I64, _I, _I, _U, ctypes.POINTER(rbf_options), _P, _P],
+    "rbf_compute_weights": [_P, _P, _I64, _I, _P, _P, _I64, _I, _P, _I, _U, ctypes.POINTER(rbf_options), _P, _P],
     "rbf_assemble_csr": [_P, _I64, _P, _P, _P, _I, _I64, _I, _P, _P, _P],
     "rbf_batched_workspace": [ctypes.POINTER(rbf_domain_desc), _I, ctypes.POINTER(_SZ)],
     "rbf_compute_weights_batched": [_P, ctypes.POINTER(rbf_domain_desc), _I, ctypes.POINTER(rbf_options), _P, _SZ],
@@ -214,10 +214,14 @@ def select_stencils(X: torch.Tensor, offsets: torch.Tensor, n_max: int, idx: tor
     return idx
 
 
-def compute_weights(X: torch.Tensor, offsets: torch.Tensor, idx: torch.Tensor, n_max: int, degree: int,
+def compute_weights(X: torch.Tensor, offsets: torch.Tensor, idx: torch.Tensor, n_max: int, degree,
                     ops=("lap",), precision="f64", w: torch.Tensor | None = None,
-                    status: torch.Tensor | None = None, ctx: Context | None = None, **opt):
-    """RBF-FD weights [len(ops), nnz] float64 and per-stencil status int8 [N]."""
+                    status: torch.Tensor | None = None, ctx: Context | None = None,
+                    degree_max: int | None = None, **opt):
+    """RBF-FD weights [len(ops), nnz] float64 and per-stencil status int8 [N].
+
+    degree: an int (every node) or a per-node int8 tensor [N]; with a tensor,
+    degree_max bounds its values (default 4)."""
     ctx = ctx or context(X.device)
     N, d = X.shape
     nnz = idx.numel()
@@ -227,9 +231,13 @@ def compute_weights(X: torch.Tensor, offsets: torch.Tensor, idx: torch.Tensor, n
     if status is None:
         status = torch.empty(N, dtype=torch.int8, device=X.device)
     o = options(precision=precision, **opt)
+    if isinstance(degree, torch.Tensor):
+        pdeg, dmax = _dev(degree, torch.int8, "degree"), (4 if degree_max is None else int(degree_max))
+    else:
+        pdeg, dmax = None, int(degree)
     _check(lib().rbf_compute_weights(ctx._sync_stream(), _dev(X, torch.float64, "X"), N, d,
                                      _dev(offsets, torch.int64, "offsets"), _dev(idx, torch.int32, "idx"), nnz,
-                                     int(n_max), int(degree), op_mask(ops), ctypes.byref(o),
+                                     int(n_max), pdeg, dmax, op_mask(ops), ctypes.byref(o),
                                      _dev(w, torch.float64, "w"), _dev(status, torch.int8, "status")),
            "rbf_compute_weights")
     return w, status

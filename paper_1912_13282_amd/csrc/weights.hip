@@ -42,14 +42,15 @@ extern "C" rbf_status rbf_options_default(rbf_options* opt) {
 }
 
 extern "C" rbf_status rbf_compute_weights(rbf_ctx* ctx, const double* X, int64_t N, int d, const int64_t* offsets,
-                                          const int32_t* idx, int64_t nnz, int n_max, int degree, unsigned op_mask,
-                                          const rbf_options* opt, double* w, int8_t* status) {
+                                          const int32_t* idx, int64_t nnz, int n_max, const int8_t* degree,
+                                          int degree_max, unsigned op_mask, const rbf_options* opt, double* w,
+                                          int8_t* status) {
     if (!ctx || !X || !offsets || !idx || !w || N < 1 || nnz < 1) return RBF_EINVAL;
     if (d != 2 && d != 3) return RBF_EDIM;
     unsigned opc;
     const int R = op_slots(op_mask, d, &opc);
     if (R < 0) return RBF_EINVAL;
-    if (degree < 0 || degree > 4 || n_max < 1) return RBF_EINVAL;
+    if (degree_max < 0 || degree_max > 4 || n_max < 1) return RBF_EINVAL;
     if (n_max > N) return RBF_ETOOFEW;
     rbf_options o;
     rbf_options_default(&o);
@@ -58,7 +59,7 @@ extern "C" rbf_status rbf_compute_weights(rbf_ctx* ctx, const double* X, int64_t
     if (o.precision != RBF_PREC_F64 && o.precision != RBF_PREC_F32_IR) return RBF_EINVAL;
     if (o.precision == RBF_PREC_F32_IR && !status) return RBF_EINVAL;  // the fallback list lives in status
     if (o.max_refine < 0 || o.scale_mode < 0 || o.scale_mode > 1 || !(o.refine_tol >= 0.0)) return RBF_EINVAL;
-    const int m = n_mono(d, degree);
+    const int m = n_mono(d, degree_max);
     const rbf::ClassEntry* c = rbf::find_class(n_max + m);
     if (!c) return RBF_EUNSUPPORTED;
     // the refined form exists for systems up to 64 unknowns; larger ones are solved in float64
@@ -68,7 +69,8 @@ extern "C" rbf_status rbf_compute_weights(rbf_ctx* ctx, const double* X, int64_t
     a.X = X;
     a.N = N;
     a.d = d;
-    a.P = degree;
+    a.P = degree_max;
+    a.degree = degree;
     a.offsets = offsets;
     a.idx = idx;
     a.nnz = nnz;

@@ -21,7 +21,7 @@ __global__ __launch_bounds__(256, 3) void k_weights_f64(StencilArgs a, int64_t N
     if (node >= N) return;
     // one call site: a second one would duplicate the unrolled solver
     if (select && a.status[node] != select) return;
-    stencil_f64_rows<MAXM, false>(a, node, a.P, lds[wv]);
+    stencil_f64_rows<MAXM, false>(a, node, node_degree(a, node), lds[wv]);
     if (select && lane_id() == 0 && a.status[node] == RBF_ST_OK) a.status[node] = (int8_t)select;
 }
 
@@ -33,7 +33,7 @@ __global__ __launch_bounds__(256, 3) void k_weights_quad(StencilArgs a, int64_t 
     const int64_t node = blockIdx.x;
     if (node >= N) return;
     if (select && a.status[node] != select) return;  // uniform
-    stencil_f64_quad<MAXM / 2>(a, node, a.P, lds);
+    stencil_f64_quad<MAXM / 2>(a, node, node_degree(a, node), lds);
     if (select && threadIdx.x == 0 && a.status[node] == RBF_ST_OK) a.status[node] = (int8_t)select;
 }
 
@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256, 3) void k_weights_ir(StencilArgs a, int64_t N,
     const int wv = threadIdx.x / WAVE;
     const int64_t node = (int64_t)blockIdx.x * 4 + wv;
     if (node >= N) return;
-    stencil_ir_rows<MAXM, false>(a, node, a.P, lds[wv], max_refine, refine_tol);
+    stencil_ir_rows<MAXM, false>(a, node, node_degree(a, node), lds[wv], max_refine, refine_tol);
 }
 
 using LaunchFn = hipError_t (*)(const StencilArgs&, int64_t, int, int, double, hipStream_t);

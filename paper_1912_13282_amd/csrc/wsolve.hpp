@@ -202,7 +202,8 @@ struct StencilArgs {
     const double* X;
     int64_t N;
     int d;
-    int P;       // augmentation degree (uniform launches); per-node launches override it
+    int P;       // uniform augmentation degree, or the bound on the per-node degrees
+    const int8_t* degree = nullptr;  // per-node augmentation degree [N], or NULL (every node P)
     const int64_t* offsets;
     const int32_t* idx;
     int64_t nnz;
@@ -215,6 +216,14 @@ struct StencilArgs {
     double* w;
     int8_t* status;
 };
+
+// Augmentation degree of a node: the per-node value when one is given (a value
+// outside [0, P] gives -1, which the prologue rejects as BADSIZE), else P.
+__device__ __forceinline__ int node_degree(const StencilArgs& a, int64_t node) {
+    if (!a.degree) return a.P;
+    const int p = a.degree[node];
+    return (p >= 0 && p <= a.P) ? p : -1;
+}
 
 // NaN weights and a status for a stencil rejected up front
 __device__ inline void reject_stencil(const StencilArgs& a, int64_t node, int64_t off, int64_t n, int8_t st) {

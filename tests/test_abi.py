@@ -55,7 +55,7 @@ def test_host_argument_errors_without_gpu(lib_path):
     assert L.rbf_select_stencils_workspace(ctypes.c_int64(1000), 3, 10, None) == -1              # EINVAL
     assert L.rbf_select_stencils_workspace(ctypes.c_int64(1000), 3, 10, ctypes.byref(b)) == 0
     assert b.value > 1000 * (4 + 8 * 3)
-    assert L.rbf_compute_weights(None, None, ctypes.c_int64(0), 2, None, None, ctypes.c_int64(0), 1, 2, 1,
+    assert L.rbf_compute_weights(None, None, ctypes.c_int64(0), 2, None, None, ctypes.c_int64(0), 1, None, 2, 1,
                                  None, None, None) == -1
 
 

@@ -132,6 +132,63 @@ def test_weights_parity(gpu, case, precision):
     assert E <= tol
 
 
+PER_NODE_CASES = {
+    # 2D disk, degrees 1..3, n_i in [ceil(1.5 m_i), 30]: one-row-per-lane class 48
+    "disk2d_deg123": (lambda: ns.disk(0.03, 11), (1, 3), 30, ("lap", "dx", "dy")),
+    # 3D cube minus sphere, degrees 2..4, n_i in [max(12, ceil(1.5 m_i)), 60]: the 128 class
+    "cube3d_deg234": (lambda: ns.cube_minus_sphere(1.0 / 14, 12), (2, 4), 60, ("lap", "dx", "dz")),
+}
+
+
+@pytest.mark.parametrize("case", list(PER_NODE_CASES))
+@pytest.mark.parametrize("precision", ["f64", "f32_ir"])
+def test_weights_per_node_degree(gpu, case, precision):
+    """One rbf_compute_weights call with a degree and a stencil size per node
+    (Sec. 3.2: the augmentation is a parameter of the approximation; Sec. 3.1:
+    stencils of varying size) against the oracle node by node; degrees outside
+    [0, degree_max] give BADSIZE and NaN weights."""
+    print(f"[weights per-node degree] {case} {precision}", flush=True)
+    mk, (plo, phi), nhi, ops = PER_NODE_CASES[case]
+    nd = mk()
+    d = nd.X.shape[1]
+    rng = np.random.default_rng(5)
+    P = rng.integers(plo, phi + 1, nd.N).astype(np.int8)
+    m = np.array([orbf.monomial_exponents(d, int(p)).shape[0] for p in P])
+    lo = np.maximum(12 if d == 3 else 1, np.ceil(1.5 * m)).astype(np.int64)
+    sizes = rng.integers(lo, nhi + 1)
+    off, idx, Xd, od, idxd = run_knn(nd.X, sizes, gpu, n_max=nhi)
+    Pbad = P.copy()
+    bad = rng.choice(nd.N, 5, replace=False)
+    Pbad[bad[:3]] = phi + 1        # above degree_max
+    Pbad[bad[3:]] = -1             # negative
+    w, st = rb.compute_weights(Xd, od, idxd, nhi, to_dev(Pbad, torch.int8, gpu), ops, precision=precision,
+                               degree_max=phi)
+    torch.cuda.synchronize()
+    w, st = w.cpu().numpy(), st.cpu().numpy()
+    assert np.all(st[bad] == rb.ST_BADSIZE)
+    for i in bad:
+        assert np.all(np.isnan(w[:, off[i]:off[i + 1]]))
+    good = np.setdiff1d(np.arange(nd.N), bad)
+    if precision == "f64":
+        assert np.all(st[good] == rb.ST_OK)
+        tol = 1e-10
+    else:
+        assert np.all((st[good] == rb.ST_REFINED) | (st[good] == rb.ST_FALLBACK))
+        tol = 1e-9
+    wo, sto = orbf.weights(nd.X, off, idx, P.astype(np.int64), ops)
+    assert sto.min() == 0
+    keep = np.zeros(off[-1], dtype=bool)
+    for i in good:
+        keep[off[i]:off[i + 1]] = True
+    hn = np.repeat(nd.h, np.diff(off))[keep]
+    for r, op in enumerate(ops):
+        sc = hn ** ORD[op]
+        den = max(1.0, float(np.max(np.abs(wo[r][keep]) * sc)))
+        E = float(np.max(np.abs(w[r][keep] - wo[r][keep]) * sc)) / den
+        print(f"  {op}: E = {E:.3e}", flush=True)
+        assert E <= tol
+
+
 def test_weights_phs5_and_closest_scale(gpu):
     nd = ns.unit_square_grid(1 / 24)
     off, idx, Xd, od, idxd = run_knn(nd.X, 12, gpu)
