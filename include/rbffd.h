@@ -125,6 +125,26 @@ rbf_status rbf_select_stencils(rbf_ctx* ctx, const double* X, int64_t N, int d,
                                void* workspace, size_t ws_bytes);
 
 /* ------------------------------------------------------------------------ *
+ * Stencil selection that allocates nothing and takes no workspace.
+ *
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result, kernels and stream semantics as rbf_select_stencils, with the
+ * selection buffers (grid, cell counts, node ids and coordinates in cell order)
+ * in a fixed array inside the library, RBF_SELECT_STATIC_BYTES per device,
+ * held from the library's load until the process ends.  Sizes whose
+ * rbf_select_stencils_workspace exceeds that return RBF_EWORKSPACE (about
+ * 1.6M nodes in 3D, 2.1M in 2D); nothing is launched then.  The array is
+ * resolved on each device by rbf_ctx_create.  Every call on one device uses
+ * the same array: calls that overlap on one device (several streams or
+ * contexts, several host threads) race and must be serialised by the caller.
+ * The call never calls hipMalloc/hipFree; it clears what must start at zero.
+ * ------------------------------------------------------------------------ */
+#define RBF_SELECT_STATIC_BYTES (64u * 1024u * 1024u)
+rbf_status rbf_select_stencils_static(rbf_ctx* ctx, const double* X, int64_t N, int d,
+                                      const int64_t* offsets, int n_max, int32_t* idx);
+
+/* ------------------------------------------------------------------------ *
  * RBF-FD weights, eq. (rbf-system-aug) of Sec. 2.2.2.
  *
  * For each stencil: offsets to the centre p* = X[idx[offsets[i]]], scaled by s

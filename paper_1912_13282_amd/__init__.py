@@ -3,6 +3,9 @@
 Python face of the HIP library ``librbffd.so`` (C ABI in include/rbffd.h):
 
     select_stencils  -- exact k-nearest-neighbour stencils, self first
+    select_stencils_static
+                     -- the same without a workspace (fixed library array), for
+                        callers that cannot allocate
     compute_weights  -- RBF-FD weights of the augmented PHS + monomial system
     compute_weights_wls
                      -- GWLS weights (monomial basis, Gaussian or unit weight function)
@@ -24,7 +27,7 @@ PyTorch supplies device memory and streams only.
 from ._binding import (  # noqa: F401
     OPS, ST_BADSIZE, ST_FALLBACK, ST_OK, ST_REFINED, ST_SINGULAR, ST_SURROGATE, ST_SURROGATE_REJECTED,
     Context, Domain, RbfError, assemble_csr, autotune_batched, compute_weights, compute_weights_batched, context,
-    get_plan, lib, select_stencils, set_plan, compute_weights_wls,
+    get_plan, lib, select_stencils, select_stencils_static, set_plan, compute_weights_wls,
     NODE_DIRICHLET, NODE_INTERIOR, NODE_NEUMANN, apply_operators, combine_operators, explicit_step,
     SOLVE_BADDIAG, SOLVE_BREAKDOWN, SOLVE_CONVERGED, SOLVE_MAXITER, assemble_implicit, bicgstab, bicgstab_workspace,
     MLP_NPARAM, mlp_adam, mlp_flatten, mlp_forward, mlp_grad, mlp_pack, mlp_unflatten, surrogate_dataset,

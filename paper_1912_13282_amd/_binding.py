@@ -68,6 +68,7 @@ _SIGS = {
     "rbf_ctx_destroy": [_P],
     "rbf_select_stencils_workspace": [_I64, _I, _I, ctypes.POINTER(_SZ)],
     "rbf_select_stencils": [_P, _P, _I64, _I, _P, _I, _P, _P, _SZ],
+    "rbf_select_stencils_static": [_P, _P, _I64, _I, _P, _I, _P],
     "rbf_compute_weights": [_P, _P, _I64, _I, _P, _P, _I64, _I, _P, _I, _U, ctypes.POINTER(rbf_options), _P, _P],
     "rbf_assemble_csr": [_P, _I64, _P, _P, _P, _I, _I64, _I, _P, _P, _P],
     "rbf_batched_workspace": [ctypes.POINTER(rbf_domain_desc), _I, ctypes.POINTER(_SZ)],
@@ -211,6 +212,27 @@ def select_stencils(X: torch.Tensor, offsets: torch.Tensor, n_max: int, idx: tor
     pw = _dev(workspace, torch.uint8, "workspace")
     _check(lib().rbf_select_stencils(ctx._sync_stream(), pX, N, d, po, int(n_max), pi, pw, workspace.numel()),
            "rbf_select_stencils")
+    return idx
+
+
+SELECT_STATIC_BYTES = 64 * 1024 * 1024   # RBF_SELECT_STATIC_BYTES
+
+
+def select_stencils_static(X: torch.Tensor, offsets: torch.Tensor, n_max: int, idx: torch.Tensor | None = None,
+                           ctx: Context | None = None) -> torch.Tensor:
+    """select_stencils without a workspace: the library's fixed per-device array
+    (RBF_SELECT_STATIC_BYTES) holds the selection buffers; nothing is allocated
+    besides idx when it is not given."""
+    ctx = ctx or context(X.device)
+    N, d = X.shape
+    if offsets.numel() != N + 1:
+        raise RbfError("offsets must have N+1 entries")
+    if idx is None:
+        idx = torch.empty(int(offsets[-1].item()), dtype=torch.int32, device=X.device)
+    _check(lib().rbf_select_stencils_static(ctx._sync_stream(), _dev(X, torch.float64, "X"), N, d,
+                                            _dev(offsets, torch.int64, "offsets"), int(n_max),
+                                            _dev(idx, torch.int32, "idx")),
+           "rbf_select_stencils_static")
     return idx
 
 

@@ -21,6 +21,15 @@ extern "C" rbf_status rbf_ctx_create(rbf_ctx** ctx, int device, void* hip_stream
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess) return RBF_EHIP;
     if (device < 0 || device >= count) return RBF_EINVAL;
+    {
+        // resolve this device's copy of the no-allocation scratch with the device current
+        int prev = 0;
+        if (hipGetDevice(&prev) != hipSuccess) return RBF_EHIP;
+        if (hipSetDevice(device) != hipSuccess) return RBF_EHIP;
+        const rbf_status st = rbf_select_scratch_init(device);
+        if (hipSetDevice(prev) != hipSuccess) return RBF_EHIP;
+        if (st != RBF_OK) return st;
+    }
     rbf_ctx* c = (rbf_ctx*)calloc(1, sizeof(rbf_ctx));
     if (!c) return RBF_EINVAL;
     c->device = device;

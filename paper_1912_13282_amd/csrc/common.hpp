@@ -20,6 +20,9 @@ struct rbf_ctx {
     size_t mlp_bytes;
 };
 
+// resolves the device address of the no-allocation selection scratch (knn.hip)
+rbf_status rbf_select_scratch_init(int device);
+
 #define RBF_HIP_CHECK(expr)                                   \
     do {                                                      \
         hipError_t e_ = (expr);                               \

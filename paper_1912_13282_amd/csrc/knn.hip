@@ -18,6 +18,9 @@
 
 #include <math.h>
 
+#include <algorithm>
+#include <mutex>
+
 namespace {
 
 struct GridParams {
@@ -537,17 +540,9 @@ extern "C" rbf_status rbf_select_stencils_workspace(int64_t N, int d, int n_max,
     return RBF_OK;
 }
 
-extern "C" rbf_status rbf_select_stencils(rbf_ctx* ctx, const double* X, int64_t N, int d, const int64_t* offsets,
-                                          int n_max, int32_t* idx, void* workspace, size_t ws_bytes) {
-    if (!ctx || !X || !offsets || !idx || !workspace || N < 1) return RBF_EINVAL;
-    if (d != 2 && d != 3) return RBF_EDIM;
-    if (n_max < 1 || n_max > 129) return RBF_EINVAL;
-    if (n_max > N) return RBF_ETOOFEW;
-    if (N > (int64_t)0x7FFFFFFF - 8192) return RBF_EINVAL;
-    SelWorkspace L = sel_layout(N, d);
-    if (ws_bytes < L.total) return RBF_EWORKSPACE;
-    RBF_HIP_CHECK(hipSetDevice(ctx->device));
-    char* ws = (char*)workspace;
+// Enqueues the whole selection pipeline with its buffers carved from ws (layout L).
+static rbf_status select_enqueue(rbf_ctx* ctx, const double* X, int64_t N, int d, const int64_t* offsets, int n_max,
+                                 int32_t* idx, char* ws, const SelWorkspace& L) {
     GridParams* gp = (GridParams*)(ws + L.gp);
     double* part = (double*)(ws + L.part);
     int* count = (int*)(ws + L.count);
@@ -583,4 +578,68 @@ extern "C" rbf_status rbf_select_stencils(rbf_ctx* ctx, const double* X, int64_t
                            (double)INFINITY);
     RBF_LAUNCH_CHECK();
     return RBF_OK;
+}
+
+static rbf_status select_check(rbf_ctx* ctx, const double* X, int64_t N, int d, const int64_t* offsets, int n_max,
+                               int32_t* idx) {
+    if (!ctx || !X || !offsets || !idx || N < 1) return RBF_EINVAL;
+    if (d != 2 && d != 3) return RBF_EDIM;
+    if (n_max < 1 || n_max > 129) return RBF_EINVAL;
+    if (n_max > N) return RBF_ETOOFEW;
+    if (N > (int64_t)0x7FFFFFFF - 8192) return RBF_EINVAL;
+    return RBF_OK;
+}
+
+extern "C" rbf_status rbf_select_stencils(rbf_ctx* ctx, const double* X, int64_t N, int d, const int64_t* offsets,
+                                          int n_max, int32_t* idx, void* workspace, size_t ws_bytes) {
+    const rbf_status st = select_check(ctx, X, N, d, offsets, n_max, idx);
+    if (st != RBF_OK) return st;
+    if (!workspace) return RBF_EINVAL;
+    SelWorkspace L = sel_layout(N, d);
+    if (ws_bytes < L.total) return RBF_EWORKSPACE;
+    RBF_HIP_CHECK(hipSetDevice(ctx->device));
+    return select_enqueue(ctx, X, N, d, offsets, n_max, idx, (char*)workspace, L);
+}
+
+// ------------------------------------------------------ no-allocation variant
+// The selection buffers of rbf_select_stencils_static live in this file-scope
+// array, one copy per device, held from module load to process end.  Host code
+// never uses the array's name as an address (on the host it is only a stand-in
+// symbol): the device address comes from hipGetSymbolAddress, taken once per
+// device at context creation with that device current.
+static __device__ __align__(256) unsigned char scratch[RBF_SELECT_STATIC_BYTES];
+
+namespace {
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES];
+}  // namespace
+
+// Resolves this device's copy of the scratch array (the caller has made the
+// device current).  Idempotent.
+rbf_status rbf_select_scratch_init(int device) {
+    if (device < 0 || device >= SCRATCH_MAX_DEVICES) return RBF_EINVAL;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return RBF_OK;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return RBF_EHIP;
+    g_scratch_ptr[device] = p;
+    return RBF_OK;
+}
+
+extern "C" rbf_status rbf_select_stencils_static(rbf_ctx* ctx, const double* X, int64_t N, int d,
+                                                 const int64_t* offsets, int n_max, int32_t* idx) {
+    const rbf_status st = select_check(ctx, X, N, d, offsets, n_max, idx);
+    if (st != RBF_OK) return st;
+    const SelWorkspace L = sel_layout(N, d);
+    if (L.total > (size_t)RBF_SELECT_STATIC_BYTES) return RBF_EWORKSPACE;
+    void* p;
+    {
+        if (ctx->device < 0 || ctx->device >= SCRATCH_MAX_DEVICES) return RBF_EINVAL;
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        p = g_scratch_ptr[ctx->device];
+    }
+    if (!p) return RBF_EHIP;  // the context's creation did not resolve the array
+    RBF_HIP_CHECK(hipSetDevice(ctx->device));
+    return select_enqueue(ctx, X, N, d, offsets, n_max, idx, (char*)p, L);
 }
