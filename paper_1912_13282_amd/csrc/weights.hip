@@ -62,8 +62,9 @@ extern "C" rbf_status rbf_compute_weights(rbf_ctx* ctx, const double* X, int64_t
     const int m = n_mono(d, degree_max);
     const rbf::ClassEntry* c = rbf::find_class(n_max + m);
     if (!c) return RBF_EUNSUPPORTED;
-    // the refined form exists for systems up to 64 unknowns; larger ones are solved in float64
-    const int prec = (c->maxm > 64) ? RBF_PREC_F64 : o.precision;
+    // the refined form exists for every class up to rbf::PAIR_MAXM unknowns; larger
+    // systems are solved in float64
+    const int prec = (c->maxm > rbf::PAIR_MAXM) ? RBF_PREC_F64 : o.precision;
     RBF_HIP_CHECK(hipSetDevice(ctx->device));
     rbf::StencilArgs a;
     a.X = X;

@@ -5,6 +5,7 @@
 #pragma once
 
 #include "wsolve.hpp"
+#include "wsolve_pair.hpp"
 #include "wsolve_quad.hpp"
 
 namespace rbf {
@@ -48,15 +49,37 @@ __global__ __launch_bounds__(256, 3) void k_weights_ir(StencilArgs a, int64_t N,
     stencil_ir_rows<MAXM, false>(a, node, node_degree(a, node), lds[wv], max_refine, refine_tol);
 }
 
+// FP32 Gauss-Jordan + FP64 refinement of systems above 64 unknowns: one stencil
+// per wavefront, two rows per lane; stencils not accepted are marked FALLBACK.
+template <int MAXM>
+__global__ __launch_bounds__(256, 1) void k_weights_ir_pair(StencilArgs a, int64_t N, int max_refine,
+                                                             double refine_tol) {
+    __shared__ __attribute__((aligned(16))) double lds[4][PairLds<MAXM>::TOTAL];
+    const int wv = threadIdx.x / WAVE;
+    const int64_t node = (int64_t)blockIdx.x * 4 + wv;
+    if (node >= N) return;
+    stencil_ir_pair<MAXM>(a, node, node_degree(a, node), lds[wv], max_refine, refine_tol);
+}
+
+// largest class with a refined form above 64 unknowns (two float rows per lane
+// must fit the 256 vector registers of a wave)
+constexpr int PAIR_MAXM = 104;
+
 using LaunchFn = hipError_t (*)(const StencilArgs&, int64_t, int, int, double, hipStream_t);
 
 template <int MAXM>
 hipError_t launch_class(const StencilArgs& a, int64_t N, int precision, int max_refine, double refine_tol,
                         hipStream_t s) {
     if constexpr (MAXM > 64) {
-        // systems above 64 unknowns are solved in float64 directly; the refined
-        // form reports them as FALLBACK (float64 used)
-        hipLaunchKernelGGL((k_weights_quad<MAXM>), dim3((unsigned)N), dim3(256), 0, s, a, N, 0);
+        if (precision == RBF_PREC_F32_IR && MAXM <= PAIR_MAXM) {
+            hipLaunchKernelGGL((k_weights_ir_pair<MAXM>), dim3((unsigned)((N + 3) / 4)), dim3(256), 0, s, a, N,
+                               max_refine, refine_tol);
+            hipLaunchKernelGGL((k_weights_quad<MAXM>), dim3((unsigned)N), dim3(256), 0, s, a, N, RBF_ST_FALLBACK);
+        } else {
+            // no refined form in this class: float64 directly (the refined form
+            // reports FALLBACK)
+            hipLaunchKernelGGL((k_weights_quad<MAXM>), dim3((unsigned)N), dim3(256), 0, s, a, N, 0);
+        }
     } else {
         const dim3 grid((unsigned)((N + 3) / 4)), block(256);
         if (precision == RBF_PREC_F64) {

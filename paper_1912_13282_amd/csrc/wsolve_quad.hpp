@@ -28,7 +28,7 @@ template <int H>
 struct QuadLds {
     static constexpr int M2 = 2 * H;
     static constexpr int XH = M2 * 4;               // scaled offsets, 4 doubles per node
-    static constexpr int COL = 2 * M2;              // column k of every row, two buffers
+    static constexpr int COL = 2 * 128;             // column k of all 128 rows (two row groups), two buffers
     static constexpr int PRW = M2 + NR;             // one pivot row + right-hand sides
     static constexpr int PR = 2 * PRW;              // two buffers
     static constexpr int SOL = M2 * NR;             // solution in unknown order
@@ -50,7 +50,7 @@ __device__ __forceinline__ void quad_eliminate(double (&row)[H], double (&rhs)[N
     for (int k = 0; k < M2; ++k) {
         if (k < M) {  // uniform
             const int par = k & 1;
-            double* col = lds + L::o_col + par * M2;
+            double* col = lds + L::o_col + par * 128;
             double* prow = lds + L::o_pr + par * L::PRW;
             int* cand = redi + 16 + 8 * par;  // [rg][2]: max bits, lane
             if (CH == k / H) {
