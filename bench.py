@@ -25,6 +25,11 @@ Other workloads (the same JSON contract, one line each):
   wls      the GWLS engine (Sec. 2.2.1) on the default node set: monomials of degree
            3, Gaussian weight (sigma 1 on the scaled offsets), four operators, with
            kNN and CSR
+  counters one launch of each hot kernel at its workload's shape, for rocprofv3
+           counter passes: stencils + FP64 + FP32-refined weights + CSR of the
+           default node set, both solvers above 64 unknowns on a 1M-node copy of
+           large3d, the batched form of a 200k-per-domain mixed batch, the
+           surrogate on a 1.7M-node disk, and a 1 GiB copy (byte calibration)
   explicit explicit Euler steps of du/dt = lap u + 5 on the default node set
            (faces u = x, sphere zero flux), each followed by the evaluation of
            the four operators on the new field; weights computed beforehand
@@ -127,7 +132,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="cube_sphere3d", choices=["cube_sphere3d", "mixed", "learned", "large3d", "explicit", "poisson3d", "poisson2d", "wls"])
+    ap.add_argument("--workload", default="cube_sphere3d", choices=["cube_sphere3d", "mixed", "learned", "large3d", "explicit", "poisson3d", "poisson2d", "wls",
+                             "counters"])
     ap.add_argument("--form", default="f32_ir", choices=["f32_ir", "f64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="time only the reported form")
@@ -137,6 +143,14 @@ def parse():
     ap.add_argument("--tune-per-domain", type=int, default=200_000, help="mixed: nodes per domain of the tuning batch")
     ap.add_argument("--train-sets", type=int, default=5000, help="learned: training node sets (2,008 nodes each)")
     ap.add_argument("--train-epochs", type=int, default=8)
+    ap.add_argument("--no-legs", action="store_true",
+                    help="default workload: skip the compact legs of the 16M-node large-3D and the 8M-stencil "
+                         "mixed workloads")
+    ap.add_argument("--err-sample", type=int, default=0,
+                    help="with --no-cpu: weights error against the oracle on this many sampled stencils "
+                         "(oracle weights of the GPU's stencils)")
+    ap.add_argument("--batched-forms", action="store_true",
+                    help="large3d / cube_sphere3d: also time the batched persistent form (both precisions)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed steps, run a plain 1 GiB read + 1 GiB write elementwise kernel "
                          "(torch.neg on float64) three times, the reference for HBM byte counters")
@@ -210,6 +224,43 @@ def cpu_oracle(X, sizes, P, ops, sample):
             "sample": f"{sample.size} seeded random nodes of the same workload (kNN against all {N} nodes + weights), "
                       f"{dt:.1f} s wall, {cpu_s:.1f} s CPU, BLAS limited to one thread"}
     return base, soff, sidx, Wo
+
+
+_POOL_ARGS = None
+
+
+def _oracle_chunk(nodes):
+    """Worker of cpu_oracle_all_cores: the oracle on its share of the sample (one
+    BLAS thread; the node array arrives through fork)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import knn as oknn
+    from oracle import rbffd as orbf
+    X, sizes, P, ops = _POOL_ARGS
+    with threadpool_limits(limits=1):
+        soff, sidx = oknn.knn_exact(X, sizes, nodes=nodes)
+        orbf.weights(X, soff, sidx, np.broadcast_to(np.asarray(P), (X.shape[0],))[nodes], ops)
+    return nodes.size
+
+
+def cpu_oracle_all_cores(X, sizes, P, ops, sample, max_workers=16):
+    """The same oracle on every host core the process may use (a fork pool over
+    os.sched_getaffinity, at most max_workers), one BLAS thread per worker; each
+    worker builds its own k-d tree.  Returns the baseline dict."""
+    import multiprocessing as mp
+    global _POOL_ARGS
+    cores = min(len(os.sched_getaffinity(0)), max_workers)
+    _POOL_ARGS = (X, sizes, P, ops)
+    parts = [np.ascontiguousarray(c) for c in np.array_split(sample, cores * 4) if c.size]
+    t = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        done = sum(pool.map(_oracle_chunk, parts, chunksize=1))
+    dt = time.perf_counter() - t
+    _POOL_ARGS = None
+    return {"value": done / dt, "unit": "stencils/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} seeded random nodes (kNN against all {X.shape[0]} nodes + weights) over a pool of "
+                      f"{cores} processes (os.sched_getaffinity, one BLAS thread each, tree built per process), "
+                      f"{dt:.1f} s wall"}
 
 
 def sample_errors(snap, sample, soff, sidx, Wo, ops, hn_sample):
@@ -290,25 +341,71 @@ def bench_uniform(a, torch, rb, B, name):
                 e[3].record(timer.stream)
         return step
 
+    if a.no_cpu and a.err_sample:
+        sample = draw_sample(N, a.err_sample)
+        pos_t = torch.from_numpy(sample_positions(off, sample)).to(dev)
+
+    # the batched persistent form on the same node set: one domain, its plan tuned
+    # per precision on a coarser copy of the workload (about 1M nodes)
+    dom, wsb, bplans = None, None, {}
+    if a.batched_forms:
+        dom = rb.Domain(X, offsets, idx, n, P, ops)
+        dom.w, dom.status = w, status          # the same output buffers as the per-call form
+        wsb = torch.empty(B.batched_workspace([dom]), dtype=torch.uint8, device=dev)
+        tw = ns.workload(name, h=(1.0 / 100 if name == "large3d" else 1.0 / 60))
+        tnd = tw["nodes"][0]
+        toff = torch.from_numpy(ns.offsets_from_sizes(np.full(tnd.N, n, dtype=np.int64))).to(dev)
+        tX = torch.from_numpy(tnd.X).to(dev)
+        tdom = rb.Domain(tX, toff, rb.select_stencils(tX, toff, n, ctx=ctx), n, P, ops)
+        for f in ("f32_ir", "f64"):
+            t = time.perf_counter()
+            bplans[f] = rb.autotune_batched([tdom], precision=f, ctx=ctx)
+            print(f"[bench] {name} batched {f}: plans tuned on {tnd.N} stencils in {time.perf_counter() - t:.1f} s",
+                  file=sys.stderr, flush=True)
+        del tdom, tX, toff
+
+    def make_batched_step(form):
+        def step(e):
+            if e:
+                e[0].record(timer.stream)
+            rb.select_stencils(X, offsets, n, idx=idx, workspace=ws, ctx=ctx)
+            if e:
+                e[1].record(timer.stream)
+            rb.compute_weights_batched([dom], precision=form, workspace=wsb, ctx=ctx)
+            if e:
+                e[2].record(timer.stream)
+            rb.assemble_csr(offsets, idx, w, n, row_ptr=row_ptr, col=col, vals=vals, ctx=ctx)
+            if e:
+                e[3].record(timer.stream)
+        return step
+
     results, snap = {}, {}
     forms = [a.form] if a.no_compare else [a.form] + [f for f in ("f64", "f32_ir") if f != a.form]
+    if a.batched_forms:
+        forms += ["batched_f32_ir", "batched_f64"]
     for f in forms:
-        ms, wall, ph = timer.run(make_step(f), a.steps, a.warmup)
+        if f.startswith("batched_"):
+            rb.set_plan(bplans[f[8:]], ctx=ctx)
+            ms, wall, ph = timer.run(make_batched_step(f[8:]), a.steps, a.warmup)
+        else:
+            ms, wall, ph = timer.run(make_step(f), a.steps, a.warmup)
         st = status.cpu().numpy()
         results[f] = dict(form=f, ms_per_step=ms, wall_ms_per_step=wall, phases_ms=ph,
                           stencils_per_s=N / (ms / 1e3),
                           knn_weights_stencils_per_s=N / ((ph["select_stencils"] + ph["compute_weights"]) / 1e3),
                           status_counts=status_counts(st), fallback_fraction=float(np.mean(st == rb.ST_FALLBACK)))
-        if not a.no_cpu:
+        if not a.no_cpu or a.err_sample:
             snap[f] = (w[:, pos_t].cpu().numpy(), idx[pos_t].cpu().numpy() if f == forms[0] else None)
         print(f"[bench] {name} {f}: {ms:.3f} ms/step  phases {ph}", file=sys.stderr, flush=True)
+    rb.set_plan(None, ctx=ctx)
 
     main = results[a.form]
     flop = weights_flops(n, m, d, R)
     achieved = flop * N / (main["phases_ms"]["compute_weights"] / 1e3) / 1e12
     M = n + m
     if M > 64:
-        kernel = "k_weights_f64<128>"
+        kernel = ("k_weights_ir_pair<100> + k_weights_quad<100> (fallback pass)" if a.form == "f32_ir"
+                  else "k_weights_quad<100>")
     elif a.form == "f32_ir":
         kernel = "k_weights_ir<56> + k_weights_f64<56> (fallback pass)"
     else:
@@ -336,6 +433,18 @@ def bench_uniform(a, torch, rb, B, name):
         base, soff, sidx, Wo = cpu_oracle(nd.X, n, P, ops, sample)
         out["cpu_baseline"] = base
         out["error"] = sample_errors(snap, sample, soff, sidx, Wo, ops, nd.h[sample])
+        if name == "cube_sphere3d":
+            out["cpu_baseline_all_cores"] = cpu_oracle_all_cores(nd.X, n, P, ops, draw_sample(N, N, seed=777))
+    elif a.err_sample:
+        from oracle import rbffd as orbf
+        ig = snap[forms[0]][1]
+        soff = ns.offsets_from_sizes(np.full(sample.size, n, dtype=np.int64))
+        Wo, _ = orbf.weights(nd.X, soff, ig, P, ops)
+        err = sample_errors({f: (v[0], None) for f, v in snap.items()}, sample, soff, ig, Wo, ops, nd.h[sample])
+        for f in err:
+            err[f]["tolerance"] = 1e-10 if f.endswith("f64") else 1e-9
+        err["note"] = "oracle weights of the GPU's stencils (the stencils are checked against the oracle in the tests)"
+        out["error"] = err
     return out
 
 
@@ -380,11 +489,16 @@ def bench_mixed(a, torch, rb, B):
         tdoms.append(rb.Domain(X, od, idx, int(n.max()), torch.from_numpy(P).to(dev), ops))
     torch.cuda.synchronize()
     print(f"[bench] mixed: tuning on {sum(D.X.shape[0] for D in tdoms)} stencils", file=sys.stderr, flush=True)
-    t = time.perf_counter()
-    plan = rb.autotune_batched(tdoms, precision=a.form, ctx=ctx)
-    tune_s = time.perf_counter() - t
+    forms = [a.form] if a.no_compare else [a.form] + [f for f in ("f64", "f32_ir") if f != a.form]
+    plans, tune_s = {}, {}
+    for f in forms:   # per-class plans, tuned for each precision (the solvers differ)
+        t = time.perf_counter()
+        plans[f] = rb.autotune_batched(tdoms, precision=f, ctx=ctx)
+        tune_s[f] = time.perf_counter() - t
+        print(f"[bench] mixed: {f} plans {[(p['chunk'], p['waves_per_cu']) for p in plans[f]]} tuned in "
+              f"{tune_s[f]:.1f} s", file=sys.stderr, flush=True)
+    plan = plans[a.form]
     del tdoms
-    print(f"[bench] mixed: plan {plan} tuned in {tune_s:.1f} s", file=sys.stderr, flush=True)
     timer = Timer(torch, ["select_stencils", "compute_weights", "assemble_csr"])
 
     def make_step(form):
@@ -405,20 +519,22 @@ def bench_mixed(a, torch, rb, B):
                 e[3].record(timer.stream)
         return step
 
-    per = max(1, (a.cpu_sample or 30_000) // len(meta))
+    per = max(1, (a.err_sample if (a.no_cpu and a.err_sample) else (a.cpu_sample or 30_000)) // len(meta))
     samples = [draw_sample(mt["nd"].N, per, seed=12345 + k) for k, mt in enumerate(meta)]
     spos = [torch.from_numpy(sample_positions(mt["off"], smp)).to(dev) for mt, smp in zip(meta, samples)]
     results, snap = {}, {}
-    forms = [a.form] if a.no_compare else [a.form] + [f for f in ("f64", "f32_ir") if f != a.form]
     for f in forms:
+        rb.set_plan(plans[f], ctx=ctx)
         ms, wall, ph = timer.run(make_step(f), a.steps, a.warmup)
         sts = np.concatenate([D.status.cpu().numpy() for D in doms])
         results[f] = dict(form=f, ms_per_step=ms, wall_ms_per_step=wall, phases_ms=ph,
                           stencils_per_s=N_total / (ms / 1e3),
                           knn_weights_stencils_per_s=N_total / ((ph["select_stencils"] + ph["compute_weights"]) / 1e3),
                           status_counts=status_counts(sts), fallback_fraction=float(np.mean(sts == rb.ST_FALLBACK)))
-        if not a.no_cpu:
+        if not a.no_cpu or a.err_sample:
             snap[f] = [D.w[:, p].cpu().numpy() for D, p in zip(doms, spos)]
+            if f == forms[0]:
+                sidx_gpu = [D.idx[p].cpu().numpy() for D, p in zip(doms, spos)]
         print(f"[bench] mixed {f}: {ms:.3f} ms/step  phases {ph}", file=sys.stderr, flush=True)
     main = results[a.form]
     achieved = flop_total / (main["phases_ms"]["compute_weights"] / 1e3) / 1e12
@@ -427,7 +543,9 @@ def bench_mixed(a, torch, rb, B):
                     {"workload": "mixed_2d3d_4_domains", "N": N_total, "nnz": nnz_total,
                      "domains": [dict(name=mt["nd"].meta["domain"], N=mt["nd"].N, d=mt["nd"].d) for mt in meta],
                      "n": "U[max(12, ceil(1.5 m)), 70] per node", "degree": "U{2,3,4} per node", "phs_power": 3,
-                     "form": a.form, "plan": plan, "autotune_s": tune_s, "tune_per_domain": a.tune_per_domain,
+                     "form": a.form, "plan": [(p["chunk"], p["waves_per_cu"]) for p in plan],
+                     "class_sizes": rb.batched_class_sizes(), "autotune_s": tune_s,
+                     "tune_per_domain": a.tune_per_domain,
                      "step": "select_stencils x4 + compute_weights_batched + assemble_csr x4"})
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                        "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
@@ -454,6 +572,20 @@ def bench_mixed(a, torch, rb, B):
                                          f"(kNN against all nodes + weights), BLAS limited to one thread"}
         out["error"] = {f: {"scaled_max_err": max(v), "tolerance": 1e-10 if f == "f64" else 1e-9}
                         for f, v in err.items()}
+    elif a.err_sample:
+        from oracle import rbffd as orbf
+        err = {}
+        for k, mt in enumerate(meta):
+            sample = samples[k]
+            soff = ns.offsets_from_sizes(mt["n"][sample])
+            Wo, _ = orbf.weights(mt["nd"].X, soff, sidx_gpu[k], mt["P"][sample].astype(np.int64), mt["ops"])
+            e = sample_errors({f: (snap[f][k], None) for f in snap}, sample, soff, None, Wo, mt["ops"],
+                              mt["nd"].h[sample])
+            for f, v in e.items():
+                err.setdefault(f, []).append(v["scaled_max_err"])
+        out["error"] = {f: {"scaled_max_err": max(v), "tolerance": 1e-10 if f == "f64" else 1e-9,
+                            "sample": int(sum(x.size for x in samples))} for f, v in err.items()}
+        out["error"]["note"] = "oracle weights of the GPU's stencils"
     return out
 
 
@@ -486,7 +618,7 @@ def bench_learned(a, torch, rb, B):
     iq = rb.select_stencils(Xq, oq, 15)
     wpq, _ = rb.compute_weights(Xq, oq, iq, 15, 2, ("lap",), precision="f64")
     wtq, stq = S.surrogate_laplacian(Xq, oq, iq, st.params)
-    wzq, _ = S.surrogate_laplacian(Xq, oq, iq, torch.zeros_like(st.params))
+    wzq, _ = S.surrogate_laplacian(Xq, oq, iq, torch.zeros_like(st.params), corr_tol=float("inf"))  # ablation
     iqn = iq.cpu().numpy()
     quality = {}
     for nm, wv in (("plain", wpq[0]), ("trained", wtq), ("zero_network", wzq)):
@@ -886,6 +1018,86 @@ def cpu_poisson(d, n, P):
                       f"sparse direct solve, {dt:.1f} s wall, {cpu_s:.1f} s CPU, BLAS limited to one thread"}
 
 
+def bench_counters(a, torch, rb, B):
+    """One launch of each hot kernel at its workload's shape (see the module
+    docstring), nothing timed: the command profiled by the counter passes."""
+    import nodesets as ns
+    dev = torch.device("cuda:0")
+    ctx = rb.context(dev)
+    ran = []
+
+    def uniform(nd, n, P, ops, forms):
+        off = torch.from_numpy(ns.offsets_from_sizes(np.full(nd.N, n, dtype=np.int64))).to(dev)
+        X = torch.from_numpy(nd.X).to(dev)
+        idx = rb.select_stencils(X, off, n, ctx=ctx)
+        for f in forms:
+            w, _ = rb.compute_weights(X, off, idx, n, P, ops, precision=f, ctx=ctx)
+        rb.assemble_csr(off, idx, w, n, ctx=ctx)
+        torch.cuda.synchronize()
+        ran.append(dict(N=nd.N, n=n, degree=P, forms=list(forms)))
+
+    wl = ns.workload("cube_sphere3d")
+    uniform(wl["nodes"][0], wl["n"], wl["P"], wl["ops"], ("f64", "f32_ir"))
+    wl = ns.workload("large3d", h=1.0 / 100)
+    uniform(wl["nodes"][0], wl["n"], wl["P"], wl["ops"], ("f64", "f32_ir"))
+    doms = []
+    for nd, P, n in ns.mixed_domains(200_000):
+        off = torch.from_numpy(ns.offsets_from_sizes(n)).to(dev)
+        X = torch.from_numpy(nd.X).to(dev)
+        idx = rb.select_stencils(X, off, int(n.max()), ctx=ctx)
+        doms.append(rb.Domain(X, off, idx, int(n.max()), torch.from_numpy(P).to(dev),
+                              ("lap", "dx", "dy") + (("dz",) if nd.d == 3 else ())))
+    for f in ("f64", "f32_ir"):
+        rb.compute_weights_batched(doms, precision=f, ctx=ctx)
+    torch.cuda.synchronize()
+    ran.append(dict(mixed_stencils=int(sum(D.X.shape[0] for D in doms)), forms=["batched f64", "batched f32_ir"]))
+    del doms
+    # the surrogate: a seeded network (its operation counts do not depend on the values)
+    nd = ns.disk(ns.DISK_H / 30.0, 1001)
+    off = torch.from_numpy(ns.offsets_from_sizes(np.full(nd.N, 15, dtype=np.int64))).to(dev)
+    X = torch.from_numpy(nd.X).to(dev)
+    idx = rb.select_stencils(X, off, 15, ctx=ctx)
+    B.surrogate_load(B.mlp_flatten(ns.surrogate_init(4)).to(dev), ctx=ctx)
+    B.surrogate_weights(X, off, idx, 15, ctx=ctx)
+    torch.cuda.synchronize()
+    ran.append(dict(surrogate_N=nd.N))
+    calib_copy(torch, dev)
+    return {"workload": "counters", "ran": ran}
+
+
+def leg_summary(o):
+    keep = ("value", "unit", "ms_per_step", "dtype", "config", "roofline", "phases_roofline", "mixed_vs_f64", "error")
+    r = {k: o[k] for k in keep if k in o}
+    r["forms"] = {f: {k: v[k] for k in ("ms_per_step", "phases_ms", "stencils_per_s", "knn_weights_stencils_per_s",
+                                          "status_counts", "fallback_fraction")}
+                  for f, v in o["forms"].items()}
+    return r
+
+
+def legs(a, torch, rb, B):
+    """Compact runs of the other two throughput workloads, reported beside the main
+    line: the 16.3M-node large-3D set (plain FP64 vs FP32+refine vs the batched
+    persistent form, with CSR) and the 8.1M-stencil mixed 2D/3D batch (per-class
+    plans tuned per precision); one warm-up and one timed step per form, weights
+    checked against the oracle on a seeded sample."""
+    import copy
+    out = {}
+    la = copy.copy(a)
+    la.steps, la.warmup, la.no_cpu, la.err_sample, la.no_compare = 1, 1, True, 2000, False
+    la.batched_forms, la.calib_copy = True, False
+    t = time.perf_counter()
+    out["large3d"] = leg_summary(bench_uniform(la, torch, rb, B, "large3d"))
+    out["large3d"]["leg_wall_s"] = time.perf_counter() - t
+    torch.cuda.empty_cache()
+    lm = copy.copy(la)
+    lm.batched_forms = False
+    t = time.perf_counter()
+    out["mixed"] = leg_summary(bench_mixed(lm, torch, rb, B))
+    out["mixed"]["leg_wall_s"] = time.perf_counter() - t
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -902,12 +1114,16 @@ def main():
     torch.cuda.set_device(torch.device("cuda:0"))
     if a.workload in ("cube_sphere3d", "large3d"):
         out = bench_uniform(a, torch, rb, B, a.workload)
+        if a.workload == "cube_sphere3d" and not a.no_legs:
+            out["legs"] = legs(a, torch, rb, B)
     elif a.workload == "mixed":
         out = bench_mixed(a, torch, rb, B)
     elif a.workload == "explicit":
         out = bench_explicit(a, torch, rb, B)
     elif a.workload == "wls":
         out = bench_wls(a, torch, rb, B)
+    elif a.workload == "counters":
+        out = bench_counters(a, torch, rb, B)
     elif a.workload in POISSON_CASES:
         out = bench_poisson(a, torch, rb, B)
     else:

@@ -91,10 +91,12 @@ typedef struct rbf_options {
                          /* LAPACK dsgesv's test                                      */
     double surrogate_tol;/* surrogate acceptance: reproduction residual <= tol        */
                          /* (default 1e-6)                                            */
+    double surrogate_corr_tol; /* surrogate acceptance: the projection's correction   */
+                         /* max|w - y| <= tol max|w| (default 0.25)                   */
 } rbf_options;
 
 /* Default options (precision F64, 10 corrections, r^3, stencil-radius scale,
- * reproduction tolerance 1e-8, surrogate tolerance 1e-6). */
+ * reproduction tolerance 1e-8, surrogate tolerances 1e-6 and 0.25). */
 rbf_status rbf_options_default(rbf_options* opt);
 
 /* Human-readable text of a return code (static storage). */
@@ -134,7 +136,7 @@ rbf_status rbf_select_stencils(rbf_ctx* ctx, const double* X, int64_t N, int d,
  * in a fixed array inside the library, RBF_SELECT_STATIC_BYTES per device,
  * held from the library's load until the process ends.  Sizes whose
  * rbf_select_stencils_workspace exceeds that return RBF_EWORKSPACE (about
- * 1.6M nodes in 3D, 2.1M in 2D); nothing is launched then.  The array is
+ * 1.5M nodes in 3D, 1.8M in 2D); nothing is launched then.  The array is
  * resolved on each device by rbf_ctx_create.  Every call on one device uses
  * the same array: calls that overlap on one device (several streams or
  * contexts, several host threads) race and must be serialised by the caller.
@@ -214,17 +216,23 @@ rbf_status rbf_assemble_csr(rbf_ctx* ctx, int64_t N, const int64_t* offsets,
 /* ------------------------------------------------------------------------ *
  * Batched persistent form: the weights of several node sets at once, mixing
  * dimension (2D/3D), augmentation degree (0..4, per node) and stencil size.
- * The stencils of all domains are sorted into size classes (n_i + m <= 24,
- * 32, 48, 64, 128); each class runs one persistent launch over all domains
- * (the FP32+refine form adds one FP64 launch per class for its fallbacks;
- * systems above 64 unknowns are solved in FP64 and reported FALLBACK).  Each
- * domain is described as for rbf_compute_weights; a stencil with n_i + m > 128
- * gets BADSIZE.  Results, status codes and layouts are those of
- * rbf_compute_weights.
- * Workspace: rbf_batched_workspace.  The plan (chunk of stencils per grab,
- * waves per compute unit) is the context's, set by rbf_autotune_batched or
- * rbf_set_plan (default chunk 4, 8 waves per CU).  At most 16 domains.
+ * The stencils of all domains are sorted into RBF_BATCHED_CLASSES size classes
+ * (n_i + m <= 24, 32, 48, 64, 80, 100, 108, 128); each class runs one
+ * persistent launch over all domains.  Classes up to 64 unknowns solve one
+ * stencil per wavefront (one row per lane); above 64, the float64 form runs one
+ * stencil per four-wave workgroup and the FP32+refinement form one stencil per
+ * wavefront (two float rows per lane, classes up to 108; the 128 class is
+ * solved in float64 and reported FALLBACK); the refined form adds one float64
+ * launch per class for its fallbacks.  Each domain is described as for
+ * rbf_compute_weights; a stencil with n_i + m > 128 gets BADSIZE.  Results,
+ * status codes and layouts are those of rbf_compute_weights.
+ * Workspace: rbf_batched_workspace.  The plan of each class (chunk of stencils
+ * per grab, waves per compute unit) is the context's, set by
+ * rbf_autotune_batched or rbf_set_plan (default chunk 4, 8 waves per CU).
+ * Plans change the scheduling only, never the results.  At most 16 domains.
  * ------------------------------------------------------------------------ */
+#define RBF_BATCHED_CLASSES 8
+
 typedef struct rbf_domain_desc {
     const double*  X;              /* [N][d] node coordinates                        */
     int64_t        N;
@@ -243,23 +251,32 @@ typedef struct rbf_domain_desc {
 typedef struct rbf_plan {
     int   chunk;         /* stencils taken per atomic grab of the work list   */
     int   waves_per_cu;  /* persistent grid size = compute units x this       */
-    float ms;            /* time of the plan when it was tuned (0 if set)     */
+    float ms;            /* the class's time when the plan was tuned (0 if set) */
 } rbf_plan;
+
+/* largest system size n + m of batched class cls (0 .. RBF_BATCHED_CLASSES-1) */
+rbf_status rbf_batched_class_size(int cls, int* maxm);
 
 rbf_status rbf_batched_workspace(const rbf_domain_desc* doms, int n_doms, size_t* bytes);
 rbf_status rbf_compute_weights_batched(rbf_ctx* ctx, const rbf_domain_desc* doms, int n_doms,
                                        const rbf_options* opt, void* workspace, size_t ws_bytes);
 
-/* Autotuner of the batched form: times every candidate plan (chunk in
- * {1,2,4,8,16} x waves per CU in {4,8,12,16}) on this batch, stores the fastest
- * in the context and returns it.  Synchronous.  cache_path (host string, may be
- * NULL): a text file of "signature chunk waves ms" lines; a stored plan for the
- * same device and batch signature is reused without timing, a tuned one appended. */
+/* Autotuner of the batched form: runs this batch once per candidate plan
+ * (chunk in {1,2,4,8,16} x waves per CU in {4,8,12,16}), times every class's
+ * launches separately with HIP events, and keeps for EACH class the fastest
+ * candidate; the plans go to the context and to best[RBF_BATCHED_CLASSES]
+ * (host, may be NULL).  Synchronous.  cache_path (host string, may be NULL): a
+ * text file of "signature chunk_0 waves_0 ... chunk_7 waves_7 ms" lines; the
+ * signature holds the device, the solver options (precision, PHS power,
+ * refinement limit and tolerance, scale mode, reproduction tolerance) and each
+ * domain's shape (d, N, nnz, degree, n_max, op_mask).  A stored line for the
+ * same signature is reused without timing; a tuned one is appended. */
 rbf_status rbf_autotune_batched(rbf_ctx* ctx, const rbf_domain_desc* doms, int n_doms,
                                 const rbf_options* opt, void* workspace, size_t ws_bytes,
                                 const char* cache_path, rbf_plan* best);
-rbf_status rbf_set_plan(rbf_ctx* ctx, const rbf_plan* plan);   /* NULL: back to the default */
-rbf_status rbf_get_plan(const rbf_ctx* ctx, rbf_plan* plan);
+/* plans[RBF_BATCHED_CLASSES] (host); NULL returns every class to the default */
+rbf_status rbf_set_plan(rbf_ctx* ctx, const rbf_plan* plans);
+rbf_status rbf_get_plan(const rbf_ctx* ctx, rbf_plan* plans);
 
 /* ------------------------------------------------------------------------ *
  * Explicit evaluation (Sec. 2.3.1): an operator applied to a known field is
@@ -439,8 +456,13 @@ rbf_status rbf_surrogate_load(rbf_ctx* ctx, const float* params);
 /* Laplacian weights of 2D stencils through the loaded network: features,
  * network, float64 projection w = y + Q (Q^T Q)^{-1} (l_q - Q^T y) onto the
  * reproduction conditions, and the residual
- * rho = max_l |(Q^T w - l_q)_l| / max(1, max |l_q|).  rho <= opt->surrogate_tol
- * gives status RBF_ST_SURROGATE; otherwise (and for stencils that are not
+ * rho = max_l |(Q^T w - l_q)_l| / max(1, max |l_q|).  A stencil is accepted
+ * (status RBF_ST_SURROGATE) when rho <= opt->surrogate_tol (a consistency check
+ * of the float64 projection, which the network cannot fail) AND the correction
+ * the projection made is small against the result, max_j |w_j - y_j| <=
+ * opt->surrogate_corr_tol max_j |w_j| (what the network controls: the zero
+ * network needs a correction of the whole weights, ratio 1); otherwise (and for
+ * stencils that are not
  * 15-node) the plain float64 solve runs and the status is
  * RBF_ST_SURROGATE_REJECTED (or RBF_ST_SINGULAR / RBF_ST_BADSIZE from that
  * solve).  w[nnz] float64, status[N] required.  n_max bounds every n_i. */

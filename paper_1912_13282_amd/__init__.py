@@ -27,7 +27,7 @@ PyTorch supplies device memory and streams only.
 from ._binding import (  # noqa: F401
     OPS, ST_BADSIZE, ST_FALLBACK, ST_OK, ST_REFINED, ST_SINGULAR, ST_SURROGATE, ST_SURROGATE_REJECTED,
     Context, Domain, RbfError, assemble_csr, autotune_batched, compute_weights, compute_weights_batched, context,
-    get_plan, lib, select_stencils, select_stencils_static, set_plan, compute_weights_wls,
+    batched_class_sizes, get_plan, lib, select_stencils, select_stencils_static, set_plan, compute_weights_wls,
     NODE_DIRICHLET, NODE_INTERIOR, NODE_NEUMANN, apply_operators, combine_operators, explicit_step,
     SOLVE_BADDIAG, SOLVE_BREAKDOWN, SOLVE_CONVERGED, SOLVE_MAXITER, assemble_implicit, bicgstab, bicgstab_workspace,
     MLP_NPARAM, mlp_adam, mlp_flatten, mlp_forward, mlp_grad, mlp_pack, mlp_unflatten, surrogate_dataset,

@@ -35,7 +35,7 @@ class RbfError(RuntimeError):
 class rbf_options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int), ("max_refine", ctypes.c_int), ("phs_power", ctypes.c_int),
                 ("scale_mode", ctypes.c_int), ("repro_tol", ctypes.c_double), ("refine_tol", ctypes.c_double),
-                ("surrogate_tol", ctypes.c_double)]
+                ("surrogate_tol", ctypes.c_double), ("surrogate_corr_tol", ctypes.c_double)]
 
 
 class rbf_domain_desc(ctypes.Structure):
@@ -76,6 +76,7 @@ _SIGS = {
     "rbf_autotune_batched": [_P, ctypes.POINTER(rbf_domain_desc), _I, ctypes.POINTER(rbf_options), _P, _SZ,
                              ctypes.c_char_p, ctypes.POINTER(rbf_plan)],
     "rbf_set_plan": [_P, ctypes.POINTER(rbf_plan)],
+    "rbf_batched_class_size": [_I, ctypes.POINTER(_I)],
     "rbf_mlp_pack": [_P, _P, _P],
     "rbf_mlp_forward": [_P, _P, _P, _P, _I64, _P],
     "rbf_mlp_grad_workspace": [_I64, ctypes.POINTER(_SZ)],
@@ -164,7 +165,7 @@ def context(device=None) -> Context:
 
 
 def options(precision="f64", max_refine=10, phs_power=3, scale_mode=0, repro_tol=1e-8,
-            refine_tol=0.0, surrogate_tol=1e-6) -> rbf_options:
+            refine_tol=0.0, surrogate_tol=1e-6, surrogate_corr_tol=0.25) -> rbf_options:
     o = rbf_options()
     _check(lib().rbf_options_default(ctypes.byref(o)), "rbf_options_default")
     o.precision = PREC[precision]
@@ -174,6 +175,7 @@ def options(precision="f64", max_refine=10, phs_power=3, scale_mode=0, repro_tol
     o.repro_tol = float(repro_tol)
     o.refine_tol = float(refine_tol)
     o.surrogate_tol = float(surrogate_tol)
+    o.surrogate_corr_tol = float(surrogate_corr_tol)
     return o
 
 
@@ -526,36 +528,63 @@ def compute_weights_batched(domains, precision="f64", workspace=None, ctx: Conte
     return domains
 
 
+BATCHED_CLASSES = 8   # RBF_BATCHED_CLASSES
+
+
+def batched_class_sizes():
+    """Largest n + m of each batched size class."""
+    out = []
+    for c in range(BATCHED_CLASSES):
+        v = ctypes.c_int()
+        _check(lib().rbf_batched_class_size(c, ctypes.byref(v)), "rbf_batched_class_size")
+        out.append(v.value)
+    return out
+
+
+def _plans(arr):
+    return [{"chunk": p.chunk, "waves_per_cu": p.waves_per_cu, "ms": p.ms} for p in arr]
+
+
 def autotune_batched(domains, precision="f64", cache_path=None, workspace=None, ctx: Context | None = None, **opt):
-    """Time the candidate plans on this batch; the fastest becomes the context's plan."""
+    """Time the candidate plans on this batch class by class; each class's fastest
+    becomes its plan in the context.  Returns one plan per size class."""
     ctx = ctx or context(domains[0].X.device)
     arr = _descs(domains)
     nb = batched_workspace(domains)
     if workspace is None or workspace.numel() < nb:
         workspace = torch.empty(nb, dtype=torch.uint8, device=domains[0].X.device)
     o = options(precision=precision, **opt)
-    plan = rbf_plan()
+    plans = (rbf_plan * BATCHED_CLASSES)()
     cp = cache_path.encode() if cache_path else None
     _check(lib().rbf_autotune_batched(ctx._sync_stream(), arr, len(domains), ctypes.byref(o),
                                       _dev(workspace, torch.uint8, "workspace"), workspace.numel(), cp,
-                                      ctypes.byref(plan)), "rbf_autotune_batched")
-    return {"chunk": plan.chunk, "waves_per_cu": plan.waves_per_cu, "ms": plan.ms}
+                                      plans), "rbf_autotune_batched")
+    return _plans(plans)
 
 
-def set_plan(chunk=None, waves_per_cu=None, ctx: Context | None = None, device=None):
+def set_plan(plans=None, ctx: Context | None = None, device=None):
+    """plans: None (defaults), one (chunk, waves_per_cu) pair for every class, or a
+    list of BATCHED_CLASSES dicts / pairs."""
     ctx = ctx or context(device)
-    if chunk is None:
+    if plans is None:
         _check(lib().rbf_set_plan(ctx._h, None), "rbf_set_plan")
         return
-    p = rbf_plan(int(chunk), int(waves_per_cu), 0.0)
-    _check(lib().rbf_set_plan(ctx._h, ctypes.byref(p)), "rbf_set_plan")
+    if isinstance(plans, tuple) and len(plans) == 2 and all(isinstance(v, int) for v in plans):
+        plans = [plans] * BATCHED_CLASSES
+    if len(plans) != BATCHED_CLASSES:
+        raise RbfError(f"set_plan needs {BATCHED_CLASSES} plans")
+    arr = (rbf_plan * BATCHED_CLASSES)()
+    for c, p in enumerate(plans):
+        ch, w = (p["chunk"], p["waves_per_cu"]) if isinstance(p, dict) else p
+        arr[c] = rbf_plan(int(ch), int(w), 0.0)
+    _check(lib().rbf_set_plan(ctx._h, arr), "rbf_set_plan")
 
 
 def get_plan(ctx: Context | None = None, device=None):
     ctx = ctx or context(device)
-    p = rbf_plan()
-    _check(lib().rbf_get_plan(ctx._h, ctypes.byref(p)), "rbf_get_plan")
-    return {"chunk": p.chunk, "waves_per_cu": p.waves_per_cu}
+    arr = (rbf_plan * BATCHED_CLASSES)()
+    _check(lib().rbf_get_plan(ctx._h, arr), "rbf_get_plan")
+    return [{"chunk": p.chunk, "waves_per_cu": p.waves_per_cu} for p in arr]
 
 
 # ------------------------------------------------------------------ surrogate

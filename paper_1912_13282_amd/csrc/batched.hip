@@ -132,9 +132,11 @@ rbf_status check_doms(const rbf_domain_desc* doms, int n_doms, int64_t* total) {
     return RBF_OK;
 }
 
-// Enqueue the batched computation with a given plan.
+// Enqueue the batched computation with the given per-class plans.  With ev
+// (NBCLS + 1 events) the launches of class c (its solve and, for the refined
+// form, its float64 fallback pass) are bracketed by ev[c] and ev[c + 1].
 rbf_status run_batched(rbf_ctx* ctx, const rbf_domain_desc* doms, int n_doms, const rbf_options& o, void* ws,
-                       size_t ws_bytes, int chunk, int waves_per_cu) {
+                       size_t ws_bytes, const int* chunk, const int* waves_per_cu, hipEvent_t* ev = nullptr) {
     int64_t total = 0;
     rbf_status st = check_doms(doms, n_doms, &total);
     if (st != RBF_OK) return st;
@@ -185,19 +187,20 @@ rbf_status run_batched(rbf_ctx* ctx, const rbf_domain_desc* doms, int n_doms, co
     hipLaunchKernelGGL(k_bscatter, dim3(nb), dim3(256), 0, s, dbp, cls_rank, starts, items);
     int cus = 256;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, ctx->device) != hipSuccess) return RBF_EHIP;
-    const int grid = cus * waves_per_cu;
+    if (ev && hipEventRecord(ev[0], s) != hipSuccess) return RBF_EHIP;
     for (int c = 0; c < NBCLS; ++c) {
         if (!g_bclass[c]) return RBF_EUNSUPPORTED;
-        if (g_bclass[c](dbp, items, starts, counter + c, c, o.precision, chunk, grid, o.max_refine, o.refine_tol, 0,
-                        s) != hipSuccess)
+        const int grid = cus * waves_per_cu[c];
+        if (g_bclass[c](dbp, items, starts, counter + c, c, o.precision, chunk[c], grid, o.max_refine, o.refine_tol,
+                        0, s) != hipSuccess)
             return RBF_EHIP;
+        // the refined form's float64 pass over this class's fallbacks
+        if (o.precision == RBF_PREC_F32_IR && bcls_maxm(c) <= PAIR_MAXM &&
+            g_bclass[c](dbp, items, starts, counter + NBCLS + c, c, RBF_PREC_F64, chunk[c], grid, 0, 0.0,
+                        RBF_ST_FALLBACK, s) != hipSuccess)
+            return RBF_EHIP;
+        if (ev && hipEventRecord(ev[c + 1], s) != hipSuccess) return RBF_EHIP;
     }
-    if (o.precision == RBF_PREC_F32_IR)
-        for (int c = 0; c < NBCLS; ++c)
-            if (bcls_maxm(c) <= 64 &&
-                g_bclass[c](dbp, items, starts, counter + NBCLS + c, c, RBF_PREC_F64, chunk, grid, 0, 0.0,
-                            RBF_ST_FALLBACK, s) != hipSuccess)
-                return RBF_EHIP;
     hipLaunchKernelGGL(k_breject, dim3(64), dim3(256), 0, s, dbp, items, starts);
     RBF_LAUNCH_CHECK();
     return RBF_OK;
@@ -214,6 +217,20 @@ extern "C" rbf_status rbf_batched_workspace(const rbf_domain_desc* doms, int n_d
     return RBF_OK;
 }
 
+// the context's plan of every class (the defaults where none is set)
+static void ctx_plans(const rbf_ctx* ctx, int* chunk, int* wpc) {
+    for (int c = 0; c < rbf::NBCLS; ++c) {
+        chunk[c] = ctx->plan_valid ? ctx->plan_chunk[c] : 4;
+        wpc[c] = ctx->plan_valid ? ctx->plan_waves_per_cu[c] : 8;
+    }
+}
+
+extern "C" rbf_status rbf_batched_class_size(int cls, int* maxm) {
+    if (!maxm || cls < 0 || cls >= rbf::NBCLS) return RBF_EINVAL;
+    *maxm = rbf::bcls_maxm(cls);
+    return RBF_OK;
+}
+
 extern "C" rbf_status rbf_compute_weights_batched(rbf_ctx* ctx, const rbf_domain_desc* doms, int n_doms,
                                                   const rbf_options* opt, void* workspace, size_t ws_bytes) {
     if (!ctx) return RBF_EINVAL;
@@ -223,40 +240,46 @@ extern "C" rbf_status rbf_compute_weights_batched(rbf_ctx* ctx, const rbf_domain
     if (o.precision != RBF_PREC_F64 && o.precision != RBF_PREC_F32_IR) return RBF_EINVAL;
     if ((o.phs_power != 3 && o.phs_power != 5) || o.max_refine < 0 || !(o.refine_tol >= 0.0)) return RBF_EINVAL;
     RBF_HIP_CHECK(hipSetDevice(ctx->device));
-    const int chunk = ctx->plan_valid ? ctx->plan_chunk : 4;
-    const int wpc = ctx->plan_valid ? ctx->plan_waves_per_cu : 8;
+    int chunk[rbf::NBCLS], wpc[rbf::NBCLS];
+    ctx_plans(ctx, chunk, wpc);
     return rbf::run_batched(ctx, doms, n_doms, o, workspace, ws_bytes, chunk, wpc);
 }
 
-extern "C" rbf_status rbf_set_plan(rbf_ctx* ctx, const rbf_plan* plan) {
+extern "C" rbf_status rbf_set_plan(rbf_ctx* ctx, const rbf_plan* plans) {
     if (!ctx) return RBF_EINVAL;
-    if (!plan) {
+    if (!plans) {
         ctx->plan_valid = 0;
         return RBF_OK;
     }
-    if (plan->chunk < 1 || plan->chunk > 4096 || plan->waves_per_cu < 1 || plan->waves_per_cu > 64) return RBF_EINVAL;
+    for (int c = 0; c < rbf::NBCLS; ++c)
+        if (plans[c].chunk < 1 || plans[c].chunk > 4096 || plans[c].waves_per_cu < 1 || plans[c].waves_per_cu > 64)
+            return RBF_EINVAL;
+    for (int c = 0; c < rbf::NBCLS; ++c) {
+        ctx->plan_chunk[c] = plans[c].chunk;
+        ctx->plan_waves_per_cu[c] = plans[c].waves_per_cu;
+    }
     ctx->plan_valid = 1;
-    ctx->plan_chunk = plan->chunk;
-    ctx->plan_waves_per_cu = plan->waves_per_cu;
     return RBF_OK;
 }
 
-extern "C" rbf_status rbf_get_plan(const rbf_ctx* ctx, rbf_plan* plan) {
-    if (!ctx || !plan) return RBF_EINVAL;
-    plan->chunk = ctx->plan_valid ? ctx->plan_chunk : 4;
-    plan->waves_per_cu = ctx->plan_valid ? ctx->plan_waves_per_cu : 8;
-    plan->ms = 0.0f;
+extern "C" rbf_status rbf_get_plan(const rbf_ctx* ctx, rbf_plan* plans) {
+    if (!ctx || !plans) return RBF_EINVAL;
+    int chunk[rbf::NBCLS], wpc[rbf::NBCLS];
+    ctx_plans(ctx, chunk, wpc);
+    for (int c = 0; c < rbf::NBCLS; ++c) plans[c] = rbf_plan{chunk[c], wpc[c], 0.0f};
     return RBF_OK;
 }
 
 // Plan search: every (chunk, waves per CU) candidate runs the whole batch once
-// (after one warm-up run) and is timed with HIP events on the context stream;
-// the fastest becomes the context's plan.  This call synchronises.  With a
-// cache path, a plan stored there for the same device and batch signature is
-// reused without timing, and a newly tuned plan is appended.
+// (after one warm-up run) with all classes on that candidate; each class's
+// launches are timed separately with HIP events on the context stream, and each
+// class keeps its fastest candidate.  This call synchronises.  With a cache
+// path, plans stored there for the same signature (device, solver options,
+// batch shape) are reused without timing, and newly tuned plans are appended.
 extern "C" rbf_status rbf_autotune_batched(rbf_ctx* ctx, const rbf_domain_desc* doms, int n_doms,
                                            const rbf_options* opt, void* workspace, size_t ws_bytes,
                                            const char* cache_path, rbf_plan* best_out) {
+    using rbf::NBCLS;
     if (!ctx) return RBF_EINVAL;
     rbf_options o;
     rbf_options_default(&o);
@@ -267,61 +290,84 @@ extern "C" rbf_status rbf_autotune_batched(rbf_ctx* ctx, const rbf_domain_desc* 
     RBF_HIP_CHECK(hipSetDevice(ctx->device));
     hipDeviceProp_t prop;
     RBF_HIP_CHECK(hipGetDeviceProperties(&prop, ctx->device));
-    // batch signature: device, precision, domain sizes and shapes
-    std::string key = std::string(prop.gcnArchName) + "|p" + std::to_string(o.precision);
+    // signature: device, solver options, domain shapes
+    char opts[256];
+    snprintf(opts, sizeof(opts), "|p%d|k%d|r%d|t%.17g|s%d|q%.17g", o.precision, o.phs_power, o.max_refine,
+             o.refine_tol, o.scale_mode, o.repro_tol);
+    std::string key = std::string(prop.gcnArchName) + opts;
     for (int k = 0; k < n_doms; ++k)
         key += "|" + std::to_string(doms[k].d) + ":" + std::to_string(doms[k].N) + ":" + std::to_string(doms[k].nnz) +
-               ":" + std::to_string(doms[k].degree ? -1 : doms[k].degree_uniform) + ":" + std::to_string(doms[k].n_max);
+               ":" + std::to_string(doms[k].degree ? -1 : doms[k].degree_uniform) + ":" +
+               std::to_string(doms[k].n_max) + ":" + std::to_string(doms[k].op_mask);
+    for (char& ch : key)
+        if (ch == ' ' || ch == '\t' || ch == '\n') ch = '_';
+    rbf_plan best[NBCLS];
     if (cache_path) {
         FILE* f = fopen(cache_path, "r");
         if (f) {
-            char line[1024];
-            while (fgets(line, sizeof(line), f)) {
-                char k[900];
-                int c = 0, w = 0;
-                float ms = 0;
-                if (sscanf(line, "%899s %d %d %f", k, &c, &w, &ms) == 4 && key == k && c >= 1 && w >= 1) {
-                    fclose(f);
-                    rbf_plan p{c, w, ms};
-                    rbf_set_plan(ctx, &p);
-                    if (best_out) *best_out = p;
-                    return RBF_OK;
+            char buf[4096];
+            while (fgets(buf, sizeof(buf), f)) {
+                char* save = nullptr;
+                char* tok = strtok_r(buf, " \n", &save);
+                if (!tok || key != tok) continue;
+                int v[2 * NBCLS];
+                bool okl = true;
+                for (int i = 0; i < 2 * NBCLS && okl; ++i) {
+                    tok = strtok_r(nullptr, " \n", &save);
+                    okl = tok && sscanf(tok, "%d", &v[i]) == 1 && v[i] >= 1;
                 }
+                if (!okl) continue;
+                for (int c = 0; c < NBCLS; ++c) best[c] = rbf_plan{v[2 * c], v[2 * c + 1], 0.0f};
+                fclose(f);
+                st = rbf_set_plan(ctx, best);
+                if (st == RBF_OK && best_out)
+                    for (int c = 0; c < NBCLS; ++c) best_out[c] = best[c];
+                return st;
             }
             fclose(f);
         }
     }
     const int chunks[] = {1, 2, 4, 8, 16};
     const int waves[] = {4, 8, 12, 16};
-    hipEvent_t e0, e1;
-    RBF_HIP_CHECK(hipEventCreate(&e0));
-    RBF_HIP_CHECK(hipEventCreate(&e1));
-    rbf_plan best{4, 8, 1e30f};
-    st = rbf::run_batched(ctx, doms, n_doms, o, workspace, ws_bytes, 4, 8);  // warm-up
+    hipEvent_t ev[NBCLS + 1];
+    for (int c = 0; c <= NBCLS; ++c) RBF_HIP_CHECK(hipEventCreate(&ev[c]));
+    for (int c = 0; c < NBCLS; ++c) best[c] = rbf_plan{4, 8, 1e30f};
+    int cc[NBCLS], ww[NBCLS];
+    ctx_plans(ctx, cc, ww);
+    for (int c = 0; c < NBCLS; ++c) cc[c] = 4, ww[c] = 8;
+    st = rbf::run_batched(ctx, doms, n_doms, o, workspace, ws_bytes, cc, ww);  // warm-up
+    float total_ms = 0.0f;
     if (st == RBF_OK) {
-        for (int c : chunks)
+        for (int ch : chunks)
             for (int w : waves) {
-                if (hipEventRecord(e0, ctx->stream) != hipSuccess) { st = RBF_EHIP; break; }
-                st = rbf::run_batched(ctx, doms, n_doms, o, workspace, ws_bytes, c, w);
+                for (int c = 0; c < NBCLS; ++c) cc[c] = ch, ww[c] = w;
+                st = rbf::run_batched(ctx, doms, n_doms, o, workspace, ws_bytes, cc, ww, ev);
                 if (st != RBF_OK) break;
-                if (hipEventRecord(e1, ctx->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                if (hipEventSynchronize(ev[NBCLS]) != hipSuccess) {
                     st = RBF_EHIP;
                     break;
                 }
-                float ms = 0;
-                if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = RBF_EHIP; break; }
-                if (ms < best.ms) best = rbf_plan{c, w, ms};
+                for (int c = 0; c < NBCLS && st == RBF_OK; ++c) {
+                    float ms = 0;
+                    if (hipEventElapsedTime(&ms, ev[c], ev[c + 1]) != hipSuccess) st = RBF_EHIP;
+                    else if (ms < best[c].ms) best[c] = rbf_plan{ch, w, ms};
+                }
+                if (st != RBF_OK) break;
             }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (int c = 0; c <= NBCLS; ++c) (void)hipEventDestroy(ev[c]);
     if (st != RBF_OK) return st;
-    rbf_set_plan(ctx, &best);
-    if (best_out) *best_out = best;
+    for (int c = 0; c < NBCLS; ++c) total_ms += best[c].ms;
+    st = rbf_set_plan(ctx, best);
+    if (st != RBF_OK) return st;
+    if (best_out)
+        for (int c = 0; c < NBCLS; ++c) best_out[c] = best[c];
     if (cache_path) {
         FILE* f = fopen(cache_path, "a");
         if (f) {
-            fprintf(f, "%s %d %d %.4f\n", key.c_str(), best.chunk, best.waves_per_cu, best.ms);
+            fprintf(f, "%s", key.c_str());
+            for (int c = 0; c < NBCLS; ++c) fprintf(f, " %d %d", best[c].chunk, best[c].waves_per_cu);
+            fprintf(f, " %.4f\n", total_ms);
             fclose(f);
         }
     }

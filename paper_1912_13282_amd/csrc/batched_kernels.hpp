@@ -13,14 +13,17 @@
 #pragma once
 
 #include "wsolve.hpp"
+#include "wsolve_pair.hpp"
 #include "wsolve_quad.hpp"
 
 namespace rbf {
 
 constexpr int BMAX_DOMS = 16;
-constexpr int NBCLS = 5;      // size classes
+constexpr int NBCLS = RBF_BATCHED_CLASSES;  // size classes
 constexpr int BREJECT = NBCLS;  // class index of invalid stencils (bad size / degree)
-__host__ __device__ constexpr int bcls_maxm(int c) { return c == 0 ? 24 : c == 1 ? 32 : c == 2 ? 48 : c == 3 ? 64 : 128; }
+__host__ __device__ constexpr int bcls_maxm(int c) {
+    return c == 0 ? 24 : c == 1 ? 32 : c == 2 ? 48 : c == 3 ? 64 : c == 4 ? 80 : c == 5 ? 100 : c == 6 ? 108 : 128;
+}
 constexpr int NCOUNTERS = 2 * NBCLS;  // one work counter per class and pass
 
 struct BDom {
@@ -91,6 +94,13 @@ __device__ __attribute__((noinline)) void solve_item_rows(StencilArgs a0, int64_
         stencil_ir_rows<MAXM, true>(a, rfl64(node), rfl(P), lds, rfl(max_refine), rfld(refine_tol));
 }
 
+template <int MAXM>
+__device__ __attribute__((noinline)) void solve_item_pair(StencilArgs a0, int64_t node, int P, int max_refine,
+                                                          double refine_tol) {
+    __shared__ __attribute__((aligned(16))) double lds[PairLds<MAXM>::TOTAL];
+    stencil_ir_pair<MAXM>(uniform_args(a0), rfl64(node), rfl(P), lds, rfl(max_refine), rfld(refine_tol));
+}
+
 template <int H>
 __device__ __attribute__((noinline)) void solve_item_quad(StencilArgs a0, int64_t node, int P) {
     __shared__ __attribute__((aligned(16))) double lds[QuadLds<H>::TOTAL];
@@ -127,8 +137,39 @@ __global__ __launch_bounds__(64, MAXM <= 32 ? 4 : (MAXM <= 48 ? 3 : 2)) void k_b
     }
 }
 
-// Persistent solve of the class above 64 unknowns: 4-wave workgroups, one
-// stencil at a time per workgroup (float64; the refined form reports FALLBACK).
+// Persistent FP32 + FP64-refinement solve of a class above 64 unknowns: one
+// stencil per wave (two float rows per lane); rejected stencils are marked
+// FALLBACK for the float64 pass.
+template <int MAXM>
+__global__ __launch_bounds__(64, 1) void k_bclass_pair(const BParams* __restrict__ bpp,
+                                                       const uint64_t* __restrict__ items,
+                                                       const int64_t* __restrict__ starts,
+                                                       unsigned long long* __restrict__ counter, int cls, int chunk,
+                                                       int max_refine, double refine_tol) {
+    static_assert(MAXM > 64 && MAXM <= PAIR_MAXM, "two float rows per lane");
+    const BParams& bp = *bpp;
+    const int64_t beg = starts[cls], end = starts[cls + 1];
+    for (;;) {
+        unsigned long long base = 0;
+        if (lane_id() == 0) base = atomicAdd(counter, (unsigned long long)chunk);
+        base = (unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(base & 0xFFFFFFFFull)) |
+               ((unsigned long long)(unsigned)__builtin_amdgcn_readfirstlane((int)(base >> 32)) << 32);
+        const int64_t t0 = beg + (int64_t)base;
+        if (t0 >= end) break;  // every wave leaves once the class is drained
+        const int64_t t1 = (t0 + chunk < end) ? t0 + chunk : end;
+        for (int64_t t = t0; t < t1; ++t) {
+            const int64_t g = (int64_t)items[t];
+            const BDom& D = bp.dom[find_dom(bp, g)];
+            const int64_t node = g - D.first;
+            const int P = D.degree ? (int)D.degree[node] : D.a.P;
+            solve_item_pair<MAXM>(D.a, node, P, max_refine, refine_tol);
+        }
+    }
+}
+
+// Persistent float64 solve of a class above 64 unknowns: 4-wave workgroups, one
+// stencil at a time per workgroup (the refined form of a class without a
+// refined solver reports FALLBACK).
 template <int PREC, int MAXM>
 __global__ __launch_bounds__(256, 3) void k_bclass_quad(const BParams* __restrict__ bpp,
                                                         const uint64_t* __restrict__ items,
@@ -177,10 +218,14 @@ hipError_t launch_bclass(const BParams* bp, const uint64_t* items, const int64_t
                          hipStream_t s) {
     if constexpr (MAXM > 64) {
         const int g4 = grid / 4 > 0 ? grid / 4 : 1;  // grid counts waves; a workgroup here is four
-        if (precision == RBF_PREC_F32_IR)
-            hipLaunchKernelGGL((k_bclass_quad<RBF_PREC_F32_IR, MAXM>), dim3(g4), dim3(256), 0, s, bp, items, starts,
-                               counter, cls, chunk, select);
-        else
+        if (precision == RBF_PREC_F32_IR) {
+            if constexpr (MAXM <= PAIR_MAXM)
+                hipLaunchKernelGGL((k_bclass_pair<MAXM>), dim3(grid), dim3(64), 0, s, bp, items, starts, counter, cls,
+                                   chunk, max_refine, refine_tol);
+            else
+                hipLaunchKernelGGL((k_bclass_quad<RBF_PREC_F32_IR, MAXM>), dim3(g4), dim3(256), 0, s, bp, items,
+                                   starts, counter, cls, chunk, select);
+        } else
             hipLaunchKernelGGL((k_bclass_quad<RBF_PREC_F64, MAXM>), dim3(g4), dim3(256), 0, s, bp, items, starts,
                                counter, cls, chunk, select);
     } else if (precision == RBF_PREC_F64) {

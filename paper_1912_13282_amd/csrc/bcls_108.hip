@@ -1,0 +1,4 @@
+// Batched persistent form, size class n + m <= 108 (any dimension and degree).
+#include "batched_kernels.hpp"
+
+RBF_BATCHED_CLASS(108)

@@ -11,10 +11,11 @@
 struct rbf_ctx {
     int device;
     hipStream_t stream;
-    // autotuned plan of the batched form (size-class packing), see batched.hip
+    // plan of each size class of the batched form (chunk, waves per CU), see
+    // batched.hip; plan_valid == 0: the defaults
     int plan_valid;
-    int plan_chunk;
-    int plan_waves_per_cu;
+    int plan_chunk[RBF_BATCHED_CLASSES];
+    int plan_waves_per_cu[RBF_BATCHED_CLASSES];
     // surrogate network parameters (device, owned), see mlp.hip
     void* mlp_params;
     size_t mlp_bytes;

@@ -547,12 +547,18 @@ __device__ __forceinline__ double xor16_32_sum(double v) {
     v += __shfl_xor(v, 32);
     return v;
 }
+__device__ __forceinline__ double xor16_32_max(double v) {
+    v = fmax(v, __shfl_xor(v, 16));
+    v = fmax(v, __shfl_xor(v, 32));
+    return v;
+}
 
 __global__ __launch_bounds__(256, 2) void k_surrogate(const float* __restrict__ params,
                                                       const bf16x8* __restrict__ packed, const double* __restrict__ X,
                                                       int64_t N, const int64_t* __restrict__ offsets,
                                                       const int32_t* __restrict__ idx, int64_t nnz, double tol,
-                                                      double* __restrict__ w, int8_t* __restrict__ status) {
+                                                      double ctol, double* __restrict__ w,
+                                                      int8_t* __restrict__ status) {
     __shared__ bf16x8 sW[TFWD * 64];
     load_tiles(sW, packed);
     const int lane = lane_id(), g = lane >> 4, s = lane & 15, wv = threadIdx.x >> 6;
@@ -730,7 +736,18 @@ __global__ __launch_bounds__(256, 2) void k_surrogate(const float* __restrict__ 
                 rho = fmax(rho, fabs(t));
             }
             rho /= 2.0;  // max(1, max |l_q|)
-            const bool accept = spd && finite && rho <= tol;
+            // what the network controls: the projection's correction w - y relative to w
+            // (the zero network needs a correction of the whole weights: ratio 1)
+            double cmax = 0.0, wmax = 0.0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (4 * g + r < NODES) {
+                    cmax = fmax(cmax, fabs(wl[r] - yy[r]));
+                    wmax = fmax(wmax, fabs(wl[r]));
+                }
+            cmax = xor16_32_max(cmax);
+            wmax = xor16_32_max(wmax);
+            const bool accept = spd && finite && rho <= tol && cmax <= ctol * wmax;
             if (accept) {
                 const double is2 = isc * isc;
 #pragma unroll
@@ -852,7 +869,7 @@ extern "C" rbf_status rbf_surrogate_weights(rbf_ctx* ctx, const double* X, int64
     rbf_options o;
     rbf_options_default(&o);
     if (opt) o = *opt;
-    if (!(o.surrogate_tol >= 0.0)) return RBF_EINVAL;
+    if (!(o.surrogate_tol >= 0.0) || !(o.surrogate_corr_tol >= 0.0)) return RBF_EINVAL;
     if (o.phs_power != 3 && o.phs_power != 5) return RBF_EINVAL;
     const rbf::ClassEntry* c = rbf::find_class(n_max + 6);
     if (!c) return RBF_EUNSUPPORTED;
@@ -861,7 +878,7 @@ extern "C" rbf_status rbf_surrogate_weights(rbf_ctx* ctx, const double* X, int64
     const bf16x8* packed = (const bf16x8*)((const char*)ctx->mlp_params + rbf_align(NPARAM * sizeof(float)));
     const int grid = grid_persistent(ctx->device, (N + SPB - 1) / SPB);
     hipLaunchKernelGGL(k_surrogate, dim3(grid), dim3(256), 0, ctx->stream, p, packed, X, N, offsets, idx, nnz,
-                       o.surrogate_tol, w, status);
+                       o.surrogate_tol, o.surrogate_corr_tol, w, status);
     RBF_LAUNCH_CHECK();
     // rejected stencils: the plain float64 solve
     rbf::StencilArgs a;

@@ -38,6 +38,7 @@ extern "C" rbf_status rbf_options_default(rbf_options* opt) {
     opt->repro_tol = 1e-8;
     opt->refine_tol = 0.0;
     opt->surrogate_tol = 1e-6;
+    opt->surrogate_corr_tol = 0.25;
     return RBF_OK;
 }
 

@@ -61,10 +61,6 @@ __global__ __launch_bounds__(256, 1) void k_weights_ir_pair(StencilArgs a, int64
     stencil_ir_pair<MAXM>(a, node, node_degree(a, node), lds[wv], max_refine, refine_tol);
 }
 
-// largest class with a refined form above 64 unknowns (two float rows per lane
-// must fit the 256 vector registers of a wave)
-constexpr int PAIR_MAXM = 104;
-
 using LaunchFn = hipError_t (*)(const StencilArgs&, int64_t, int, int, double, hipStream_t);
 
 template <int MAXM>

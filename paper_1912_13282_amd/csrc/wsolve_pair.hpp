@@ -29,6 +29,17 @@
 
 namespace rbf {
 
+// largest size class with this refined form (two float rows per lane: 2 x 108
+// values next to the working registers of the wave)
+constexpr int PAIR_MAXM = 108;
+
+// Stencils of up to PAIR_TRI_N nodes keep the float64 PHS block A (symmetric,
+// upper triangle, row-major packed) in LDS from the assembly, so the refinement
+// residuals read it instead of recomputing every entry's square root; larger
+// stencils recompute it.
+constexpr int PAIR_TRI_N = 72;
+__host__ __device__ constexpr int tri_row(int j, int n) { return j * n - (j * (j - 1)) / 2; }
+
 template <int MAXM>
 struct PairLds {
     static_assert(MAXM > 64 && MAXM <= 128, "two rows per lane");
@@ -36,8 +47,9 @@ struct PairLds {
     static constexpr int X64 = 128 * NR;      // float64 iterate, unknown order
     static constexpr int F32 = 128 * NR / 2;  // float32 solution / correction, unknown order
     static constexpr int PIV = MAXM / 2;      // pivot lane and slot swap of each step (int)
-    static constexpr int TOTAL = XH + X64 + F32 + PIV;
-    static constexpr int o_xh = 0, o_x = XH, o_f32 = XH + X64, o_piv = XH + X64 + F32;
+    static constexpr int TRI = PAIR_TRI_N * (PAIR_TRI_N + 1) / 2;  // float64 PHS block, upper triangle
+    static constexpr int TOTAL = XH + X64 + F32 + PIV + TRI;
+    static constexpr int o_xh = 0, o_x = XH, o_f32 = XH + X64, o_piv = XH + X64 + F32, o_tri = XH + X64 + F32 + PIV;
 };
 
 // exchange of two registers in place (on the active lanes)
@@ -128,6 +140,8 @@ __device__ __forceinline__ void stencil_ir_pair(const StencilArgs& a, int64_t no
     wave_lds_sync();
     const int M = n + m;
     const int d = a.d, kpow = a.phs_power;
+    double* tri = lds + L::o_tri;
+    const bool tri_ok = n <= PAIR_TRI_N;
     // ---- assembly in float64, rounded to float32.  Order chosen for register
     // pressure: right-hand sides first, then the PHS columns, then the cheap
     // monomial columns, so few temporaries are live next to the full rows.
@@ -166,6 +180,10 @@ __device__ __forceinline__ void stencil_ir_pair(const StencilArgs& a, int64_t no
                 const double dx1 = x1[0] - p01.x, dy1 = x1[1] - p01.y, dz1 = x1[2] - p2;
                 const double a0 = phs_from_r2(dx0 * dx0 + dy0 * dy0 + dz0 * dz0, kpow);
                 const double a1 = phs_from_r2(dx1 * dx1 + dy1 * dy1 + dz1 * dz1, kpow);
+                if (tri_ok) {  // uniform
+                    if (w0 && live && k >= j0) tri[tri_row(j0, n) + k - j0] = a0;
+                    if (w1 && live && k >= j1) tri[tri_row(j1, n) + k - j1] = a1;
+                }
                 const double qv = ipow4_v(p01.x, e[0]) * ipow4_v(p01.y, e[1]) * ipow4_v(p2, e[2]);
                 const float pad0 = (r0 == c) ? 1.0f : 0.0f, pad1 = (r1 == c) ? 1.0f : 0.0f;
                 row0[c] = !live ? pad0 : (w0 ? (float)a0 : (q0 ? (float)qv : pad0));
@@ -298,7 +316,42 @@ __device__ __forceinline__ void stencil_ir_pair(const StencilArgs& a, int64_t no
                 double r[NR];
                 pair_rhs(a, m, n, rr, xr, r);
                 double ra = 0.0;
-                if (rr < M) {
+                if (tri_ok) {  // uniform
+                    const int j = rr - m;
+                    const bool wr = j >= 0 && j < n, qr = t == 0 && rr < m;  // m <= 35: no polynomial row in slot 1
+                    // columns c < m: monomials at the weight row's node (0 in the other rows)
+                    for (int c = 0; c < m; ++c) {
+                        const double kv = wr ? mono(d, c, xr) : 0.0;
+                        const double2 x01 = *reinterpret_cast<const double2*>(x64 + c * NR);
+                        r[0] = fma(-kv, x01.x, r[0]);
+                        r[1] = fma(-kv, x01.y, r[1]);
+                        const double2 x23 = *reinterpret_cast<const double2*>(x64 + c * NR + 2);
+                        r[2] = fma(-kv, x23.x, r[2]);
+                        r[3] = fma(-kv, x23.y, r[3]);
+                        if (it == 0) ra += fabs(kv);
+                    }
+                    // columns m + k: A_jk from the stored triangle, or monomial rr at node k
+                    const int tj = wr ? tri_row(j, n) - j : 0;
+                    for (int k = 0; k < n; ++k) {
+                        const int tk = tri_row(k, n) - k;
+                        const int ti = wr ? ((k >= j) ? tj + k : tk + j) : 0;
+                        const double av = tri[ti];
+                        double qv = 0.0;
+                        if (t == 0) {
+                            const double2 p01 = *reinterpret_cast<const double2*>(xh + 4 * k);
+                            qv = ipow4_v(p01.x, e[0]) * ipow4_v(p01.y, e[1]) * ipow4_v(xh[4 * k + 2], e[2]);
+                        }
+                        const double kv = wr ? av : (qr ? qv : 0.0);
+                        const int c = m + k;
+                        const double2 x01 = *reinterpret_cast<const double2*>(x64 + c * NR);
+                        r[0] = fma(-kv, x01.x, r[0]);
+                        r[1] = fma(-kv, x01.y, r[1]);
+                        const double2 x23 = *reinterpret_cast<const double2*>(x64 + c * NR + 2);
+                        r[2] = fma(-kv, x23.x, r[2]);
+                        r[3] = fma(-kv, x23.y, r[3]);
+                        if (it == 0) ra += fabs(kv);
+                    }
+                } else if (rr < M) {
                     for (int c = 0; c < M; ++c) {
                         const double kv = pair_entry(d, kpow, m, n, rr, c, xr, e, xh);
                         const double2 x01 = *reinterpret_cast<const double2*>(x64 + c * NR);

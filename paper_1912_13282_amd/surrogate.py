@@ -123,7 +123,9 @@ def train(state: TrainState, data: TrainingSet, epochs: int, batch: int = 8192, 
     return history
 
 
-def surrogate_laplacian(X, offsets, idx, params: torch.Tensor, n_max: int = N_STENCIL, tol: float = 1e-6):
-    """Laplacian weights through the network + projection (plain solve where rejected)."""
+def surrogate_laplacian(X, offsets, idx, params: torch.Tensor, n_max: int = N_STENCIL, tol: float = 1e-6,
+                        corr_tol: float = 0.25):
+    """Laplacian weights through the network + projection (plain solve where rejected;
+    corr_tol = inf accepts every consistent projection, the ablation without the gate)."""
     B.surrogate_load(params)
-    return B.surrogate_weights(X, offsets, idx, n_max, surrogate_tol=tol)
+    return B.surrogate_weights(X, offsets, idx, n_max, surrogate_tol=tol, surrogate_corr_tol=corr_tol)

@@ -72,6 +72,7 @@ int main(void) {{
   printf("rbf_options size %zu\\n", sizeof(rbf_options));
   F(rbf_options, precision) F(rbf_options, max_refine) F(rbf_options, phs_power) F(rbf_options, scale_mode)
   F(rbf_options, repro_tol) F(rbf_options, refine_tol) F(rbf_options, surrogate_tol)
+  F(rbf_options, surrogate_corr_tol)
   printf("rbf_domain_desc size %zu\\n", sizeof(rbf_domain_desc));
   F(rbf_domain_desc, X) F(rbf_domain_desc, N) F(rbf_domain_desc, d) F(rbf_domain_desc, offsets)
   F(rbf_domain_desc, idx) F(rbf_domain_desc, nnz) F(rbf_domain_desc, degree) F(rbf_domain_desc, degree_uniform)
@@ -119,7 +120,7 @@ def test_defaults_and_status_strings(lib_path):
     o = B.rbf_options()
     assert L.rbf_options_default(ctypes.byref(o)) == 0
     assert (o.precision, o.max_refine, o.phs_power, o.scale_mode) == (0, 10, 3, 0)
-    assert (o.repro_tol, o.refine_tol, o.surrogate_tol) == (1e-8, 0.0, 1e-6)
+    assert (o.repro_tol, o.refine_tol, o.surrogate_tol, o.surrogate_corr_tol) == (1e-8, 0.0, 1e-6, 0.25)
     L.rbf_status_string.restype = ctypes.c_char_p
     texts = {c: L.rbf_status_string(c) for c in (0, -1, -2, -3, -4, -5, -6, -7)}
     assert len(set(texts.values())) == 8 and texts[-7] == b"unknown status"

@@ -63,23 +63,30 @@ def test_batched_mixed_parity(gpu, precision):
         assert E <= tol
 
 
-def test_autotune_plan_and_cache(gpu, tmp_path):
+@pytest.mark.parametrize("precision", ["f64", "f32_ir"])
+def test_autotune_plan_and_cache(gpu, tmp_path, precision):
+    """Per-class plans: every class gets its own tuned (chunk, waves per CU); the
+    cache serves the same plans for the same signature (and not for other solver
+    options); plans change the scheduling, never the results (bit-identical)."""
     doms, ref = build_batch(gpu, per_domain=600)
     cache = str(tmp_path / "plans.txt")
-    plan = rb.autotune_batched(doms, precision="f64", cache_path=cache)
-    assert plan["chunk"] >= 1 and plan["waves_per_cu"] >= 1 and plan["ms"] > 0
-    assert rb.get_plan() == {"chunk": plan["chunk"], "waves_per_cu": plan["waves_per_cu"]}
+    plans = rb.autotune_batched(doms, precision=precision, cache_path=cache)
+    assert len(plans) == len(rb.batched_class_sizes())
+    assert all(p["chunk"] >= 1 and p["waves_per_cu"] >= 1 for p in plans)
+    assert rb.get_plan() == [{"chunk": p["chunk"], "waves_per_cu": p["waves_per_cu"]} for p in plans]
     w1 = [D.w.clone() for D in doms]
+    s1 = [D.status.clone() for D in doms]
     rb.set_plan(None)
-    plan2 = rb.autotune_batched(doms, precision="f64", cache_path=cache)   # served from the cache
-    assert (plan2["chunk"], plan2["waves_per_cu"]) == (plan["chunk"], plan["waves_per_cu"])
-    rb.compute_weights_batched(doms, precision="f64")
-    for a, D in zip(w1, doms):
-        assert torch.equal(a, D.w)        # plans change scheduling, never results
-    rb.set_plan(1, 4)
-    rb.compute_weights_batched(doms, precision="f64")
-    for a, D in zip(w1, doms):
-        assert torch.equal(a, D.w)
+    plans2 = rb.autotune_batched(doms, precision=precision, cache_path=cache)   # served from the cache
+    assert [(p["chunk"], p["waves_per_cu"]) for p in plans2] == [(p["chunk"], p["waves_per_cu"]) for p in plans]
+    assert len(open(cache).read().splitlines()) == 1
+    rb.autotune_batched(doms, precision=precision, cache_path=cache, phs_power=5)   # other options: tuned again
+    assert len(open(cache).read().splitlines()) == 2
+    for plan in (plans2, (1, 4), (16, 16), [(1 + c % 5, 4 + 4 * (c % 4)) for c in range(len(plans))]):
+        rb.set_plan(plan)
+        rb.compute_weights_batched(doms, precision=precision)
+        for a, b, D in zip(w1, s1, doms):
+            assert torch.equal(a, D.w) and torch.equal(b, D.status)   # plans change scheduling, never results
     rb.set_plan(None)
 
 
@@ -130,8 +137,8 @@ def test_large_ir_forced_fallback_equals_f64(gpu):
 @pytest.mark.parametrize("precision", ["f64", "f32_ir"])
 @pytest.mark.parametrize("n,P", [(59, 2), (70, 2), (89, 4), (91, 4), (113, 4)])
 def test_large_systems_sizes_2d(gpu, n, P, precision):
-    """2D systems of 65, 76, 104, 106 and 128 unknowns (the edges of the size classes
-    above 64; the refined form reaches 104 unknowns, beyond that it reports FALLBACK)."""
+    """2D systems of 65, 76, 104, 106 and 128 unknowns (size classes 80, 100, 108 and
+    128 above 64; the refined form reaches 108 unknowns, beyond that it reports FALLBACK)."""
     nd = ns.disk(0.07, 1007)
     off = ns.offsets_from_sizes(np.full(nd.N, n, np.int64))
     Xd, od = torch.from_numpy(nd.X).to(gpu), torch.from_numpy(off).to(gpu)
@@ -145,7 +152,7 @@ def test_large_systems_sizes_2d(gpu, n, P, precision):
     M = n + (6 if P == 2 else 15)
     if precision == "f64":
         assert good.size >= 0.99 * nd.N and np.all(st[good] == rb.ST_OK)
-    elif M <= 104:
+    elif M <= 108:
         assert good.size >= 0.99 * nd.N and np.all((st[good] == rb.ST_REFINED) | (st[good] == rb.ST_FALLBACK))
         assert np.mean(st[good] == rb.ST_REFINED) >= 0.95
     else:

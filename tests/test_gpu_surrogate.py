@@ -111,7 +111,7 @@ def test_projection_parity_and_reproduction(gpu):
     nd, off, X, od, idx = _plain_and_stencils(gpu)
     flat = rb.mlp_flatten({k: torch.from_numpy(v) for k, v in p.items()}).to(gpu)
     rb.surrogate_load(flat)
-    w, st = rb.surrogate_weights(X, od, idx, 15, surrogate_tol=1e300)
+    w, st = rb.surrogate_weights(X, od, idx, 15, surrogate_tol=1e300, surrogate_corr_tol=1e300)
     feat, _, scale = rb.surrogate_dataset(X, od, idx)
     y = rb.mlp_forward(flat, rb.mlp_pack(flat), feat)
     torch.cuda.synchronize()
@@ -147,21 +147,21 @@ def test_thresholds_and_fallback(gpu):
     rb.surrogate_load(flat)
     wp, _ = rb.compute_weights(X, od, idx, 15, 2, ("lap",), precision="f64")
     # tolerance 0: a stencil passes only with an exactly zero residual; the rest are solved plainly
-    w0, s0 = rb.surrogate_weights(X, od, idx, 15, surrogate_tol=0.0)
+    w0, s0 = rb.surrogate_weights(X, od, idx, 15, surrogate_tol=0.0, surrogate_corr_tol=1e300)
     s0 = s0.cpu().numpy()
     rej = s0 == rb.ST_SURROGATE_REJECTED
     assert np.all((s0 == rb.ST_SURROGATE) | rej) and rej.mean() >= 0.99
     wr = w0.cpu().numpy().reshape(-1, 15)[rej]
     assert np.array_equal(wr, wp[0].cpu().numpy().reshape(-1, 15)[rej])   # the plain kernel, bit for bit
     # tolerance infinity: nothing rejected
-    _, s1 = rb.surrogate_weights(X, od, idx, 15, surrogate_tol=1e300)
+    _, s1 = rb.surrogate_weights(X, od, idx, 15, surrogate_tol=1e300, surrogate_corr_tol=1e300)
     assert np.all(s1.cpu().numpy() == rb.ST_SURROGATE)
     # stencils that are not 15-node go to the plain solve (sizes 15 and 16 mixed)
     sizes = np.where(np.arange(nd.N) % 7 == 0, 16, 15)
     off2 = ns.offsets_from_sizes(sizes)
     od2 = torch.from_numpy(off2).to(gpu)
     idx2 = rb.select_stencils(X, od2, 16)
-    w2, s2 = rb.surrogate_weights(X, od2, idx2, 16, surrogate_tol=1e300)
+    w2, s2 = rb.surrogate_weights(X, od2, idx2, 16, surrogate_tol=1e300, surrogate_corr_tol=1e300)
     s2 = s2.cpu().numpy()
     assert np.all(s2[sizes == 16] == rb.ST_SURROGATE_REJECTED) and np.all(s2[sizes == 15] == rb.ST_SURROGATE)
     wo, _ = orbf.weights(nd.X, off2, idx2.cpu().numpy(), 2, ("lap",))
@@ -171,11 +171,27 @@ def test_thresholds_and_fallback(gpu):
     assert E <= 1e-10
 
 
+def test_zero_network_rejected_at_default_tolerances(gpu):
+    """The acceptance test judges what the network controls: the zero network's
+    output needs a correction of the whole weights (ratio 1 > 0.25), so at the
+    default tolerances every stencil falls back to the plain solve, bit for bit;
+    a tolerance above 1 accepts them all."""
+    nd, off, X, od, idx = _plain_and_stencils(gpu)
+    wp, _ = rb.compute_weights(X, od, idx, 15, 2, ("lap",), precision="f64")
+    rb.surrogate_load(torch.zeros(rb.MLP_NPARAM, dtype=torch.float32, device=gpu))
+    w, st = rb.surrogate_weights(X, od, idx, 15)
+    assert torch.all(st == rb.ST_SURROGATE_REJECTED)
+    assert torch.equal(w, wp[0])
+    # its correction ratio is exactly 1: a tolerance just above 1 accepts every stencil
+    _, st2 = rb.surrogate_weights(X, od, idx, 15, surrogate_corr_tol=1.0 + 1e-12)
+    assert torch.all(st2 == rb.ST_SURROGATE)
+
+
 def test_zero_network_is_min_norm_projection(gpu):
     nd, off, X, od, idx = _plain_and_stencils(gpu)
     zero = torch.zeros(rb.MLP_NPARAM, dtype=torch.float32, device=gpu)
     rb.surrogate_load(zero)
-    w, st = rb.surrogate_weights(X, od, idx, 15, surrogate_tol=1e300)
+    w, st = rb.surrogate_weights(X, od, idx, 15, surrogate_tol=1e300, surrogate_corr_tol=1e300)
     idx_n = idx.cpu().numpy().reshape(-1, 15)
     Xh = nd.X[idx_n] - nd.X[idx_n[:, :1]]
     s = np.sqrt((Xh ** 2).sum(-1)).max(1)
@@ -220,7 +236,8 @@ def test_training_gain_and_resume(gpu, tmp_path):
     nd, off, X, od, idx = _plain_and_stencils(gpu)
     wp, _ = rb.compute_weights(X, od, idx, 15, 2, ("lap",), precision="f64")
     wt, stt = S.surrogate_laplacian(X, od, idx, st.params)
-    wz, stz = S.surrogate_laplacian(X, od, idx, torch.zeros_like(st.params))
+    # the ablation: the zero network's projection alone (the correction gate would reject it all)
+    wz, stz = S.surrogate_laplacian(X, od, idx, torch.zeros_like(st.params), corr_tol=float("inf"))
     idx_n = idx.cpu().numpy()
     interior = ~nd.is_boundary
     e, pe = {}, {}
@@ -239,7 +256,7 @@ def test_training_gain_and_resume(gpu, tmp_path):
           flush=True)
     print(f"  per-stencil max|w - w_plain| / max|w_plain|: trained median {np.median(dev_t):.2e} "
           f"max {dev_t.max():.2e}; zero network median {np.median(dev_z):.2e}", flush=True)
-    assert acc >= 0.99
+    assert acc >= 0.9
     assert pe["trained"] <= 3.0 * pe["plain"]
     assert pe["zero"] >= 1e3 * pe["trained"]
     assert np.median(dev_t) < 0.2 * np.median(dev_z)
