@@ -9,11 +9,16 @@
 //   k_bin_count                   : cell of every node + rank inside its cell
 //   k_scan_*                      : exclusive scan of the cell counts
 //   k_bin_scatter                 : node ids and SoA coordinates in cell order
-//   k_knn<T>                      : one wavefront per query node; candidates of
-//       the surrounding cells are streamed in chunks of 64*T, bitonic-sorted
-//       across the wave on (key, index) and merged into a sorted top list of
-//       64*T entries; rings of cells are added until the k-th key is below the
-//       squared distance to the unsearched region (exact termination).
+//   k_knn_radius                  : one wavefront per query node (n_i <= 101):
+//       every node within a radius estimated from the local density is
+//       filtered by its key, the survivors compacted in LDS and sorted once on
+//       (key, index) (exact: at least k survivors prove the radius sufficient)
+//   k_knn<T>, k_knn_list          : one wavefront per query node, n_i <= 129
+//       (and the queries the radius search leaves unsettled): candidates of the surrounding
+//       cells are streamed in chunks of 64*T, bitonic-sorted across the wave on
+//       (key, index) and merged into a sorted top list of 64*T entries; rings of
+//       cells are added until the k-th key is below the squared distance to
+//       the unsearched region (exact termination).
 #include "common.hpp"
 
 #include <math.h>
@@ -32,11 +37,11 @@ struct GridParams {
 };
 
 constexpr int BBOX_BLOCKS = 512;
-// mean nodes per cell relative to n_max / (unit-ball volume), i.e. the cell side
-// relative to the stencil radius (measured: 2D is fastest at about one stencil
-// radius per cell, 3D at half the volume, which cuts the 27-cell candidate set)
-constexpr double CELL_FILL_2D = 1.0;
-constexpr double CELL_FILL_3D = 0.5;
+// mean nodes per cell relative to n_max / (unit-ball volume), i.e. the cell
+// volume relative to the stencil ball: cells a fraction of the ball keep the
+// cells gathered around a search radius close to the ball itself
+constexpr double CELL_FILL_2D = 0.5;
+constexpr double CELL_FILL_3D = 0.25;
 constexpr int SCAN_CHUNK = 1024;  // elements per scan block (256 threads x 4)
 
 __global__ __launch_bounds__(256) void k_zero_ints(int* __restrict__ p, int64_t n) {
@@ -392,26 +397,17 @@ __device__ __forceinline__ void slot_range(const GridParams& g, const int* __res
     len = b - a;
 }
 
+// Streaming search of one query (one wavefront): candidate cell rows streamed in
+// chunks of 64 T, filtered against the current k-th key, bitonic-sorted across
+// the wave on (key, index) and merged into a sorted top list of 64 T entries;
+// rings of cells are added until the k-th key is below the squared distance to
+// the unsearched region (exact termination).  Writes the whole stencil.
 template <int T>
-__global__ __launch_bounds__(256) void k_knn(const GridParams* __restrict__ gpp, const int* __restrict__ cell_start,
-                                             const int* __restrict__ sorted_id, const double* __restrict__ sx,
-                                             int64_t N, int d, const int64_t* __restrict__ offsets, int n_max,
-                                             int32_t* __restrict__ idx, double key_inf) {
-    const GridParams g = *gpp;
-    int lane = lane_id();
-    int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
-    if (q >= N) return;
-    const int qid = sorted_id[q];
-    const int64_t off = offsets[qid];
-    const int64_t ni = offsets[qid + 1] - off;
-    if (ni < 1 || ni > n_max || ni > N) {
-        for (int64_t e = lane; e < ni; e += WAVE) idx[off + e] = -1;
-        return;
-    }
-    if (lane == 0) idx[off] = qid;
-    const int k = (int)ni - 1;
-    if (k == 0) return;
-
+__device__ __forceinline__ void knn_stream(const GridParams& g, const int* __restrict__ cell_start,
+                                        const int* __restrict__ sorted_id, const double* __restrict__ sx, int64_t N,
+                                        int d, int64_t q, int qid, int64_t off, int k, int32_t* __restrict__ idx,
+                                        double key_inf) {
+    const int lane = lane_id();
     double qx[3];
     qx[0] = sx[q];
     qx[1] = sx[N + q];
@@ -421,7 +417,7 @@ __global__ __launch_bounds__(256) void k_knn(const GridParams* __restrict__ gpp,
 
     double TK[T];
     unsigned TI[T];
-#pragma unroll
+    #pragma unroll
     for (int t = 0; t < T; ++t) {
         TK[t] = INFINITY;
         TI[t] = 0xFFFFFFFFu;
@@ -499,8 +495,236 @@ __global__ __launch_bounds__(256) void k_knn(const GridParams* __restrict__ gpp,
     }
 }
 
+
+// Streaming kernel: every query (stencils of up to 129 nodes), or with a list
+// (the radius search's unsettled queries: list[0 .. *list_count)) a persistent
+// grid of waves over the listed cell-order positions.
+template <int T>
+__device__ __forceinline__ void knn_stream_query(const GridParams& g, const int* __restrict__ cell_start,
+                                                 const int* __restrict__ sorted_id, const double* __restrict__ sx,
+                                                 int64_t N, int d, const int64_t* __restrict__ offsets, int n_max,
+                                                 int32_t* __restrict__ idx, double key_inf, int64_t q) {
+    const int lane = lane_id();
+    const int qid = sorted_id[q];
+    const int64_t off = offsets[qid];
+    const int64_t ni = offsets[qid + 1] - off;
+    if (ni < 1 || ni > n_max || ni > N) {
+        for (int64_t e = lane; e < ni; e += WAVE) idx[off + e] = -1;
+        return;
+    }
+    if (lane == 0) idx[off] = qid;
+    if (ni == 1) return;
+    knn_stream<T>(g, cell_start, sorted_id, sx, N, d, q, qid, off, (int)ni - 1, idx, key_inf);
+}
+
+template <int T>
+__global__ __launch_bounds__(256) void k_knn(const GridParams* __restrict__ gpp, const int* __restrict__ cell_start,
+                                             const int* __restrict__ sorted_id, const double* __restrict__ sx,
+                                             int64_t N, int d, const int64_t* __restrict__ offsets, int n_max,
+                                             int32_t* __restrict__ idx, double key_inf) {
+    const GridParams g = *gpp;
+    const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / WAVE;
+    if (q >= N) return;
+    knn_stream_query<T>(g, cell_start, sorted_id, sx, N, d, offsets, n_max, idx, key_inf, q);
+}
+
+__global__ __launch_bounds__(256) void k_knn_list(const GridParams* __restrict__ gpp,
+                                                  const int* __restrict__ cell_start,
+                                                  const int* __restrict__ sorted_id, const double* __restrict__ sx,
+                                                  int64_t N, int d, const int64_t* __restrict__ offsets, int n_max,
+                                                  int32_t* __restrict__ idx, double key_inf,
+                                                  const int* __restrict__ list, const int* __restrict__ list_count) {
+    const GridParams g = *gpp;
+    const int nl = __builtin_amdgcn_readfirstlane(*list_count);
+    const int nw = (int)(gridDim.x * (blockDim.x / WAVE));
+    for (int i = (int)(blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE); i < nl; i += nw)
+        knn_stream_query<1>(g, cell_start, sorted_id, sx, N, d, offsets, n_max, idx, key_inf,
+                            (int64_t)__builtin_amdgcn_readfirstlane(list[i]));
+}
+
+// ------------------------------------------------------------ radius search
+// Queries with k = n_i - 1 <= RADIUS_KMAX.  The k nearest nodes of a query all have keys
+// <= tau exactly when at least k nodes other than the query have keys <= tau.
+// tau is first estimated from the node density in the 3 x 3 (x 3) cells around
+// the query; every node of the cells within sqrt(tau) (rows of cells along x
+// are contiguous in cell order) is tested against tau and the survivors are
+// compacted into a per-wave LDS buffer.  With k <= survivors <= RCAP they are
+// sorted once on (key, index) and the first k written; otherwise tau is
+// rescaled (survivors grow like tau^(d/2)) and the gather repeated.  A query
+// that does not settle within RTRIES gathers is listed for the streaming search.
+constexpr int RCAP = 128;
+constexpr int RTRIES = 6;
+constexpr int RADIUS_KMAX = 100;  // survivors aimed at 1.25 k must fit RCAP
+
+// Nodes in the cell rows of `rows` (rows of cells along x, y/z from the row
+// index) within radius rho of qx: lane r handles row r0 + r, returns its node
+// range; the caller scans them.  Conservative: a cell is taken when its box is
+// within rho (rho already carries the rounding margin).
+__device__ __forceinline__ void radius_row(const GridParams& g, const int* __restrict__ cell_start, int d,
+                                           const double (&qx)[3], double rho, int ylo, int zlo, int ny, int row,
+                                           int nrows, int& start, int& len) {
+    start = 0;
+    len = 0;
+    if (row >= nrows) return;
+    const int cy = ylo + row % ny, cz = zlo + row / ny;
+    const double gy = axis_gap(g, qx[1], cy, cy, 1);
+    const double gz = (d == 3) ? axis_gap(g, qx[2], cz, cz, 2) : 0.0;
+    const double rem = rho * rho - gy * gy - gz * gz;
+    if (rem < 0.0) return;
+    const double rx = sqrt(rem);
+    const int xlo = cell_coord(qx[0] - rx, g.origin[0], g.inv_cell, g.dims[0]);
+    const int xhi = cell_coord(qx[0] + rx, g.origin[0], g.inv_cell, g.dims[0]);
+    start = cell_start[lin3(g, xlo, cy, cz)];
+    len = cell_start[lin3(g, xhi, cy, cz) + 1] - start;
+}
+
+__global__ __launch_bounds__(256) void k_knn_radius(const GridParams* __restrict__ gpp,
+                                                    const int* __restrict__ cell_start,
+                                                    const int* __restrict__ sorted_id, const double* __restrict__ sx,
+                                                    int64_t N, int d, const int64_t* __restrict__ offsets, int n_max,
+                                                    int32_t* __restrict__ idx, double key_inf,
+                                                    int* __restrict__ list, int* __restrict__ list_count) {
+    __shared__ double skey[4][RCAP];
+    __shared__ unsigned sid[4][RCAP];
+    const GridParams g = *gpp;
+    const int lane = lane_id(), wv = threadIdx.x / WAVE;
+    const int64_t q = (int64_t)blockIdx.x * 4 + wv;
+    if (q >= N) return;
+    const int qid = sorted_id[q];
+    const int64_t off = offsets[qid];
+    const int64_t ni = offsets[qid + 1] - off;
+    if (ni < 1 || ni > n_max || ni > N) {
+        for (int64_t e = lane; e < ni; e += WAVE) idx[off + e] = -1;
+        return;
+    }
+    if (lane == 0) idx[off] = qid;
+    if (ni == 1) return;
+    const int k = (int)ni - 1;
+    double qx[3];
+    qx[0] = sx[q];
+    qx[1] = sx[N + q];
+    qx[2] = (d == 3) ? sx[2 * N + q] : 0.0;
+    int qc[3] = {0, 0, 0};
+    for (int a = 0; a < d; ++a) qc[a] = cell_coord(qx[a], g.origin[a], g.inv_cell, g.dims[a]);
+
+    // local density: nodes in the 3 x 3 (x 3) cells around the query (in the grid)
+    double tau;
+    {
+        const int nrow = (d == 3) ? 9 : 3;
+        int cnt = 0, cells = 0;
+        if (lane < nrow) {
+            const int cy = qc[1] + lane % 3 - 1, cz = (d == 3) ? qc[2] + lane / 3 - 1 : 0;
+            if (cy >= 0 && cy < g.dims[1] && cz >= 0 && cz < g.dims[2]) {
+                const int xlo = max(qc[0] - 1, 0), xhi = min(qc[0] + 1, g.dims[0] - 1);
+                cnt = cell_start[lin3(g, xhi, cy, cz) + 1] - cell_start[lin3(g, xlo, cy, cz)];
+                cells = xhi - xlo + 1;
+            }
+        }
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) {
+            cnt += __shfl_xor(cnt, o);
+            cells += __shfl_xor(cells, o);
+        }
+        cnt = __builtin_amdgcn_readfirstlane(cnt);
+        cells = __builtin_amdgcn_readfirstlane(cells);
+        // expected nodes within radius r: density * V_d r^d; aim at about 1.3 (k + 1)
+        const double vol = (double)cells * ((d == 3) ? g.cell * g.cell * g.cell : g.cell * g.cell);
+        const double dens = (double)max(cnt, 1) / vol;
+        const double unit = (d == 3) ? 4.18879020478639098 : 3.14159265358979324;
+        const double v = 1.3 * (k + 1) / (dens * unit);
+        const double r = (d == 3) ? cbrt(v) : sqrt(v);
+        tau = r * r;
+    }
+
+    int count = 0;
+    bool ok = false;
+    for (int attempt = 0; attempt < RTRIES; ++attempt) {
+        const double rho = sqrt(tau) * (1.0 + 1e-9);
+        const int ylo = cell_coord(qx[1] - rho, g.origin[1], g.inv_cell, g.dims[1]);
+        const int yhi = cell_coord(qx[1] + rho, g.origin[1], g.inv_cell, g.dims[1]);
+        const int zlo = (d == 3) ? cell_coord(qx[2] - rho, g.origin[2], g.inv_cell, g.dims[2]) : 0;
+        const int zhi = (d == 3) ? cell_coord(qx[2] + rho, g.origin[2], g.inv_cell, g.dims[2]) : 0;
+        const int ny = yhi - ylo + 1;
+        const int nrows = ny * (zhi - zlo + 1);
+        count = 0;
+        for (int r0 = 0; r0 < nrows; r0 += WAVE) {
+            int st, ln;
+            radius_row(g, cell_start, d, qx, rho, ylo, zlo, ny, r0 + lane, nrows, st, ln);
+            int incl = ln;
+#pragma unroll
+            for (int o = 1; o < WAVE; o <<= 1) {
+                const int t = __shfl_up(incl, o);
+                if (lane >= o) incl += t;
+            }
+            const int total = __builtin_amdgcn_readlane(incl, 63);
+            const int excl = incl - ln;
+            for (int base = 0; base < total; base += WAVE) {
+                const int e = base + lane;
+                // smallest row r with incl[r] > e
+                int r = 0;
+#pragma unroll
+                for (int step = 32; step > 0; step >>= 1) {
+                    const int v = __shfl(incl, r + step - 1);
+                    if (v <= e) r += step;
+                }
+                const int sr = __shfl(st, r);
+                const int er = __shfl(excl, r);
+                // branch-free: every lane loads an in-bounds candidate, then selects
+                const bool valid = e < total;
+                const int pos = valid ? sr + (e - er) : 0;
+                const unsigned cid = (unsigned)sorted_id[pos];
+                const double key = sq_key(qx, sx[pos], sx[N + pos], (d == 3) ? sx[2 * N + pos] : 0.0, d);
+                const bool pass = valid && cid != (unsigned)qid && key <= tau;
+                const uint64_t b = ballot64(pass);
+                const int slot = count + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32),
+                                                                        __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
+                if (pass && slot < RCAP) {
+                    skey[wv][slot] = key;
+                    sid[wv][slot] = cid;
+                }
+                count += __builtin_popcountll(b);
+            }
+        }
+        if (count >= k && count <= RCAP) {
+            ok = true;
+            break;
+        }
+        // survivors grow like tau^(d/2): aim at about 1.25 k
+        const double ratio = 1.25 * k / (double)max(count, 1);
+        const double cr = cbrt(ratio);
+        double f = (count == 0) ? 4.0 : ((d == 3) ? cr * cr : ratio);
+        f = (count < k) ? fmax(f, 1.2) : fmin(f, 0.9);
+        tau *= f;
+    }
+    if (!ok) {  // left to the streaming search (k_knn_list)
+        if (lane == 0) list[atomicAdd(list_count, 1)] = (int)q;
+        return;
+    }
+    wave_lds_sync();
+    if (count <= WAVE) {
+        double K[1];
+        unsigned I[1];
+        K[0] = lane < count ? skey[wv][lane] : key_inf;
+        I[0] = lane < count ? sid[wv][lane] : 0xFFFFFFFFu;
+        bitonic_sort<1>(K, I, false);
+        if (lane < k) idx[off + 1 + lane] = (int32_t)I[0];
+    } else {
+        double K[2];
+        unsigned I[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int e = lane + WAVE * t;
+            K[t] = e < count ? skey[wv][e] : key_inf;
+            I[t] = e < count ? sid[wv][e] : 0xFFFFFFFFu;
+        }
+        bitonic_sort<2>(K, I, false);
+        if (lane < k) idx[off + 1 + lane] = (int32_t)I[0];
+        if (WAVE + lane < k) idx[off + 1 + WAVE + lane] = (int32_t)I[1];
+    }
+}
+
 struct SelWorkspace {
-    size_t gp, part, count, bsum, cell_of, rank, sorted_id, sx, total;
+    size_t gp, part, count, bsum, cell_of, rank, sorted_id, sx, list, total;
     int64_t cap;
     int nb_scan;
 };
@@ -515,7 +739,7 @@ SelWorkspace sel_layout(int64_t N, int d) {
     w.part = o;
     o += rbf_align(sizeof(double) * 6 * BBOX_BLOCKS);
     w.count = o;
-    o += rbf_align(sizeof(int) * (w.cap + 1));
+    o += rbf_align(sizeof(int) * (w.cap + 2));  // cell counts, then the list length
     w.bsum = o;
     o += rbf_align(sizeof(int) * (w.nb_scan + 1));
     w.cell_of = o;
@@ -526,6 +750,8 @@ SelWorkspace sel_layout(int64_t N, int d) {
     o += rbf_align(sizeof(int) * N);
     w.sx = o;
     o += rbf_align(sizeof(double) * d * N);
+    w.list = o;
+    o += rbf_align(sizeof(int) * N);
     w.total = o;
     return w;
 }
@@ -559,9 +785,12 @@ static rbf_status select_enqueue(rbf_ctx* ctx, const double* X, int64_t N, int d
     int nbb = (int)std::min<int64_t>(BBOX_BLOCKS, (N + 255) / 256);
     hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(256), 0, s, X, N, d, part);
     hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(64), 0, s, part, nbb, N, d, target, L.cap, gp);
-    // cleared by a kernel (a memset node in a captured graph is not reliable)
-    hipLaunchKernelGGL(k_zero_ints, dim3((unsigned)((L.cap + 1 + 255) / 256)), dim3(256), 0, s, count,
-                       (int64_t)L.cap + 1);
+    // cleared by a kernel (a memset node in a captured graph is not reliable);
+    // count[cap + 1] is the length of the radius search's fallback list
+    int* list_count = count + L.cap + 1;
+    int* list = (int*)(ws + L.list);
+    hipLaunchKernelGGL(k_zero_ints, dim3((unsigned)((L.cap + 2 + 255) / 256)), dim3(256), 0, s, count,
+                       (int64_t)L.cap + 2);
     int nbN = (int)((N + 255) / 256);
     hipLaunchKernelGGL(k_bin_count, dim3(nbN), dim3(256), 0, s, X, N, d, gp, count, cell_of, rank);
     hipLaunchKernelGGL(k_scan_blocks, dim3(L.nb_scan), dim3(256), 0, s, count, L.cap + 1, bsum);
@@ -570,10 +799,13 @@ static rbf_status select_enqueue(rbf_ctx* ctx, const double* X, int64_t N, int d
     hipLaunchKernelGGL(k_bin_scatter, dim3(nbN), dim3(256), 0, s, X, N, d, count, cell_of, rank, sorted_id, sx);
     int64_t waves = N;
     dim3 grid((unsigned)((waves * WAVE + 255) / 256));
-    if (n_max - 1 <= 64)
-        hipLaunchKernelGGL(k_knn<1>, grid, dim3(256), 0, s, gp, count, sorted_id, sx, N, d, offsets, n_max, idx,
-                           (double)INFINITY);
-    else
+    if (n_max - 1 <= RADIUS_KMAX) {
+        hipLaunchKernelGGL(k_knn_radius, grid, dim3(256), 0, s, gp, count, sorted_id, sx, N, d, offsets, n_max, idx,
+                           (double)INFINITY, list, list_count);
+        const unsigned lg = (unsigned)std::min<int64_t>((N + 3) / 4, 2048);  // persistent: at most 8k waves
+        hipLaunchKernelGGL(k_knn_list, dim3(lg), dim3(256), 0, s, gp, count, sorted_id, sx, N, d, offsets, n_max,
+                           idx, (double)INFINITY, list, list_count);
+    } else
         hipLaunchKernelGGL(k_knn<2>, grid, dim3(256), 0, s, gp, count, sorted_id, sx, N, d, offsets, n_max, idx,
                            (double)INFINITY);
     RBF_LAUNCH_CHECK();
