@@ -205,9 +205,12 @@ rbf_status rbf_compute_weights_wls(rbf_ctx* ctx, const double* X, int64_t N, int
  * CSR operator (Sec. 2.3.2, internal-node rows of eqs. implicit-start..end).
  *
  * row_ptr[N+1] (int64) = offsets; the columns of each row are the stencil
- * indices in ascending order; vals[r][nnz] holds the weights of operator r
- * permuted the same way.  n_max bounds every n_i (<= 256).  w and vals may
- * not alias.  No workspace is needed.
+ * indices in ascending order (equal columns keep their stencil order); vals[r][nnz]
+ * holds the weights of operator r permuted the same way.  n_max bounds every n_i
+ * (<= 256).  A row whose size lies outside [0, n_max], or that holds a column
+ * outside [0, N), gets col = -1 and NaN values over its range; a row whose
+ * range lies outside [0, nnz] is left unwritten.  w and vals may not alias.
+ * No workspace is needed.
  * ------------------------------------------------------------------------ */
 rbf_status rbf_assemble_csr(rbf_ctx* ctx, int64_t N, const int64_t* offsets,
                             const int32_t* idx, const double* w, int n_ops, int64_t nnz,

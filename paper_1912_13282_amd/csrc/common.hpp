@@ -177,6 +177,25 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Value of lane ^ M (M a compile-time mask of the low lane bits).  Masks inside
+// a row of 16 lanes are DPP moves: 1, 2, 3 quad permutations, 7 the half-row
+// mirror, 15 the row mirror, 8 a row rotation, 4 = 3 then 7; the others cross
+// rows and go through the LDS permute.  The partner lane must be active.
+template <int M>
+__device__ __forceinline__ unsigned lane_xor_u32(unsigned v) {
+    const int x = (int)v;
+    if constexpr (M == 1) return (unsigned)__builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false);
+    else if constexpr (M == 2) return (unsigned)__builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false);
+    else if constexpr (M == 3) return (unsigned)__builtin_amdgcn_update_dpp(x, x, 0x1B, 0xF, 0xF, false);
+    else if constexpr (M == 4) {
+        const int a = __builtin_amdgcn_update_dpp(x, x, 0x1B, 0xF, 0xF, false);
+        return (unsigned)__builtin_amdgcn_update_dpp(a, a, 0x141, 0xF, 0xF, false);
+    } else if constexpr (M == 7) return (unsigned)__builtin_amdgcn_update_dpp(x, x, 0x141, 0xF, 0xF, false);
+    else if constexpr (M == 8) return (unsigned)__builtin_amdgcn_update_dpp(x, x, 0x128, 0xF, 0xF, false);
+    else if constexpr (M == 15) return (unsigned)__builtin_amdgcn_update_dpp(x, x, 0x140, 0xF, 0xF, false);
+    else return (unsigned)__shfl_xor(x, M);
+}
+
 // lanes where pred holds (wave64), without materialising pred in a register
 __device__ __forceinline__ uint64_t ballot64(bool pred) { return __builtin_amdgcn_ballot_w64(pred); }
 

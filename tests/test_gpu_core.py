@@ -311,6 +311,47 @@ def test_csr_bit_exact(gpu, case):
     assert np.array_equal(vals.cpu().numpy(), v2)
 
 
+def test_csr_invalid_rows(gpu):
+    """Rows longer than n_max or holding a column outside [0, N) come back as
+    col = -1 and NaN values over their range; the other rows are exact."""
+    rng = np.random.default_rng(8)
+    N, n_max = 500, 20
+    sizes = rng.integers(0, n_max + 1, N)
+    sizes[[3, 17]] = n_max + 5                                   # oversize rows
+    off = ns.offsets_from_sizes(sizes.astype(np.int64))
+    idx = np.concatenate([rng.choice(N, s, replace=False) for s in sizes]).astype(np.int32)
+    bad_col = [40, 41]
+    for r in bad_col:
+        if sizes[r] == 0:
+            continue
+        idx[off[r] + sizes[r] // 2] = N + 7 if r == 40 else -1       # columns outside [0, N)
+    w = torch.randn((3, int(off[-1])), dtype=torch.float64, device=gpu)
+    rp, col, vals = rb.assemble_csr(to_dev(off, torch.int64, gpu), to_dev(idx, torch.int32, gpu), w, n_max)
+    torch.cuda.synchronize()
+    col, vals = col.cpu().numpy(), vals.cpu().numpy()
+    bad = {3, 17} | {r for r in bad_col if sizes[r] > 0}
+    good = np.array([i for i in range(N) if i not in bad])
+    for r in bad:
+        assert np.all(col[off[r]:off[r + 1]] == -1) and np.all(np.isnan(vals[:, off[r]:off[r + 1]]))
+    pos = np.concatenate([np.arange(off[i], off[i + 1]) for i in good])
+    offg = ns.offsets_from_sizes(sizes[good].astype(np.int64))
+    r2, c2, v2 = ocsr.to_csr(offg, idx[pos], w.cpu().numpy()[:, pos])
+    assert np.array_equal(col[pos], c2) and np.array_equal(vals[:, pos], v2)
+
+
+def test_csr_duplicate_columns_keep_stencil_order(gpu):
+    """Equal columns inside a row keep their stencil order (the oracle's stable sort)."""
+    rng = np.random.default_rng(9)
+    N = 300
+    sizes = rng.integers(1, 40, N)
+    off = ns.offsets_from_sizes(sizes.astype(np.int64))
+    idx = rng.integers(0, 12, int(off[-1])).astype(np.int32)      # many repeats per row
+    w = torch.randn((2, int(off[-1])), dtype=torch.float64, device=gpu)
+    rp, col, vals = rb.assemble_csr(to_dev(off, torch.int64, gpu), to_dev(idx, torch.int32, gpu), w, 40)
+    r2, c2, v2 = ocsr.to_csr(off, idx, w.cpu().numpy())
+    assert np.array_equal(col.cpu().numpy(), c2) and np.array_equal(vals.cpu().numpy(), v2)
+
+
 def test_csr_of_weights_matches_oracle(gpu):
     nd = ns.disk(0.0404, 1001)
     off, idx, Xd, od, idxd = run_knn(nd.X, 15, gpu)
