@@ -135,6 +135,8 @@ def parse():
     ap.add_argument("--workload", default="cube_sphere3d", choices=["cube_sphere3d", "mixed", "learned", "large3d", "explicit", "poisson3d", "poisson2d", "wls",
                              "counters"])
     ap.add_argument("--form", default="f32_ir", choices=["f32_ir", "f64"])
+    ap.add_argument("--precond", default="block_jacobi", choices=["block_jacobi", "jacobi", "none"],
+                    help="poisson: BiCGStab preconditioner")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="time only the reported form")
     ap.add_argument("--cpu-sample", type=int, default=None,
@@ -904,12 +906,17 @@ POISSON_CASES = {
 }
 
 
-def bicgstab_bytes_per_row(n):
+def bicgstab_bytes_per_row(n, precond="jacobi"):
     """Algorithmic HBM bytes per row of one BiCGStab iteration: two row products
     (row offset, n indices and values, the gathered vector once, the inverse
     diagonal, one dot operand, the result) and the three vector passes
-    (p: 3 reads + 1 write, s: 2 + 1, x and r: 5 + 2)."""
-    return 2 * (8 + 12.0 * n + 8 + 8 + 8 + 8) + 8 * (4 + 3 + 7)
+    (p: 3 reads + 1 write, s: 2 + 1, x and r: 5 + 2).  Block-Jacobi adds two
+    block products per row: 64 float32 entries of the inverse, the permutation
+    entry, the input and the output."""
+    b = 2 * (8 + 12.0 * n + 8 + 8 + 8 + 8) + 8 * (4 + 3 + 7)
+    if precond == "block_jacobi":
+        b += 2 * (64 * 4 + 4 + 8 + 8)
+    return b
 
 
 def bench_poisson(a, torch, rb, B):
@@ -938,8 +945,15 @@ def bench_poisson(a, torch, rb, B):
     x = torch.empty(N, dtype=torch.float64, device=dev)
     sws = torch.empty(rb.bicgstab_workspace(N), dtype=torch.uint8, device=dev)
     tol = 1e-10
-    timer = Timer(torch, ["select_stencils", "compute_weights", "assemble_implicit", "bicgstab"])
+    bj = a.precond == "block_jacobi"
+    pc = torch.empty(rb.block_jacobi_size(N, d), dtype=torch.uint8, device=dev)
+    timer = Timer(torch, ["select_stencils", "compute_weights", "assemble_implicit", "precondition", "bicgstab"])
     infos = []
+
+    def solve(precond):
+        x.zero_()
+        return rb.bicgstab(off, idx, vals, n, rhs, x=x, tol=tol, max_iter=100000, precond=precond,
+                           workspace=sws, ctx=ctx, pc=pc if precond == "block_jacobi" else None)[1]
 
     def step(e):
         if e:
@@ -953,12 +967,13 @@ def bench_poisson(a, torch, rb, B):
         rb.assemble_implicit(off, idx, w[0], kind, f=f, g=g, d=d, vals=vals, rhs=rhs, ctx=ctx)
         if e:
             e[3].record(timer.stream)
-        x.zero_()
-        _, info = rb.bicgstab(off, idx, vals, n, rhs, x=x, tol=tol, max_iter=100000, precond="jacobi",
-                              workspace=sws, ctx=ctx)
+        if bj:
+            rb.block_jacobi(X, off, idx, vals, pc=pc, ctx=ctx)
         if e:
             e[4].record(timer.stream)
-        infos.append(info)
+        infos.append(solve(a.precond))
+        if e:
+            e[5].record(timer.stream)
 
     ms, wall, ph = timer.run(step, a.steps, a.warmup)
     info = infos[-1]
@@ -966,19 +981,37 @@ def bench_poisson(a, torch, rb, B):
     print(f"[bench] {a.workload}: {ms:.2f} ms/step  phases {ph}  solve {info}  max error {err:.3e}",
           file=sys.stderr, flush=True)
     it = max(1, info["iterations"])
-    per_it = bicgstab_bytes_per_row(n) * N
-    gbs = per_it * it / (ph["bicgstab"] / 1e3) / 1e9
+    per_row = bicgstab_bytes_per_row(n, a.precond)
+    gbs = per_row * N * it / (ph["bicgstab"] / 1e3) / 1e9
+    solver = {"block_jacobi": "BiCGStab, block-Jacobi (64-node cell blocks, float32 inverses)",
+              "jacobi": "BiCGStab, Jacobi row scaling", "none": "BiCGStab, unpreconditioned"}[a.precond]
     res = base_line(a, N / (ms / 1e3), ms, "f64",
                     {"workload": f"poisson_annulus_{d}d", "N": N, "nnz": nnz, "n": n, "degree": P, "ops": ["lap"],
-                     "solver": "BiCGStab, Jacobi row scaling", "tol": tol,
-                     "step": "select_stencils + compute_weights + assemble_implicit + bicgstab"})
+                     "solver": solver, "tol": tol,
+                     "step": "select_stencils + compute_weights + assemble_implicit + precondition + bicgstab"})
     res["metric"] = "Poisson nodes solved/s (stencils + weights + assembly + BiCGStab)"
     res["unit"] = "nodes/s"
+    bja = f"k_bj_apply<false>, " if bj else ""
+    bjs = f"k_bj_apply<true>, " if bj else ""
     res["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                        "frac": gbs / PEAK_HBM_GBS, "traffic": recorded_traffic(a.workload),
-                       "kernel": f"BiCGStab iteration (k_vec<P>, k_spmv<8,{(n + 7) // 8},V>, k_vec<S>, "
-                                 f"k_spmv<8,{(n + 7) // 8},T>, k_vec<X>)",
-                       "bytes_per_row_per_iteration": bicgstab_bytes_per_row(n), "rows": N, "iterations": it}
+                       "kernel": f"BiCGStab iteration (k_vec<P>, {bja}k_spmv<8,{(n + 7) // 8},V>, k_vec<S>, "
+                                 f"{bjs}k_spmv<8,{(n + 7) // 8},T>, k_vec<X>)",
+                       "bytes_per_row_per_iteration": per_row, "rows": N, "iterations": it}
+    if not a.no_compare:
+        # the other preconditioner on the same system, one untimed-by-the-step solve
+        other = "jacobi" if bj else "block_jacobi"
+        if other == "block_jacobi":
+            rb.block_jacobi(X, off, idx, vals, pc=pc, ctx=ctx)
+        t0 = torch.cuda.Event(enable_timing=True)
+        t1 = torch.cuda.Event(enable_timing=True)
+        t0.record(timer.stream)
+        oi = solve(other)
+        t1.record(timer.stream)
+        torch.cuda.synchronize()
+        res["compare_precond"] = {"precond": other, "iterations": oi["iterations"], "status": oi["status"],
+                                  "bicgstab_ms": t0.elapsed_time(t1)}
+        print(f"[bench] {a.workload}: with {other}: {res['compare_precond']}", file=sys.stderr, flush=True)
     res["phases_ms"] = ph
     res["wall_ms_per_step"] = wall
     res["solve"] = info

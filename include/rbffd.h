@@ -359,13 +359,16 @@ rbf_status rbf_assemble_implicit(rbf_ctx* ctx, int64_t N, int d, const int64_t* 
                                  const double* f, const double* g, double* vals, double* rhs);
 
 /* iterative solver preconditioners and outcomes */
-#define RBF_PRECOND_NONE    0
-#define RBF_PRECOND_JACOBI  1   /* rows scaled by the inverse diagonal */
+#define RBF_PRECOND_NONE          0
+#define RBF_PRECOND_JACOBI        1   /* rows scaled by the inverse diagonal              */
+#define RBF_PRECOND_BLOCK_JACOBI  2   /* inverses of 64 x 64 diagonal blocks of nodes in  */
+                                      /* cell order (rbf_block_jacobi_setup), right side  */
 
 #define RBF_SOLVE_CONVERGED  0
 #define RBF_SOLVE_MAXITER    1
 #define RBF_SOLVE_BREAKDOWN  2  /* a BiCGStab denominator vanished or a value is not finite */
 #define RBF_SOLVE_BADDIAG    3  /* Jacobi: a row without a finite nonzero diagonal entry */
+#define RBF_SOLVE_DIVERGED   4  /* the residual grew past 10^6 times the initial one      */
 
 typedef struct rbf_solve_info {
     int32_t status;          /* RBF_SOLVE_*                                               */
@@ -376,24 +379,48 @@ typedef struct rbf_solve_info {
 
 /* ------------------------------------------------------------------------ *
  * Solution of M x = r (Sec. 2.3.2) by BiCGStab (van der Vorst 1992), the
- * Krylov method the paper's benchmark uses (Sec. 5), in float64 on the GPU.
+ * Krylov method the paper's benchmark uses (Sec. 5; there with an incomplete-LU
+ * preconditioner on the CPU), in float64 on the GPU.
  *
  * M: N rows in the stencil layout or CSR (row_ptr = offsets, col = idx, vals
  * [nnz]); n_max bounds the row lengths.  x[N]: initial guess in, solution out.
  * Preconditioner: RBF_PRECOND_JACOBI solves D^-1 M x = D^-1 r with D the
  * diagonal of M (the first entry of row i in column i), RBF_PRECOND_NONE with
- * D = I.  Stops when ||D^-1 (r - M x)|| <= tol ||D^-1 r|| or after max_iter
- * iterations.  Every step runs on the device (no host round trip inside an
- * iteration); the call waits for the context stream every 16 iterations and
- * on return, when *info (host memory, may be NULL) is filled.  Deterministic:
- * every dot product is reduced in a fixed order.  Workspace:
- * rbf_bicgstab_workspace (7 N + 4,096 float64 values and 256 bytes).
+ * D = I; both stop when ||D^-1 (r - M x)|| <= tol ||D^-1 r||.
+ * RBF_PRECOND_BLOCK_JACOBI solves M P^-1 y = r, x = P^-1 y, with P the block
+ * diagonal of M over the node blocks of rbf_block_jacobi_setup (pc, built from
+ * the same M), and stops when ||r - M x|| <= tol ||r||.  pc/pc_bytes are
+ * ignored by the other preconditioners (may be NULL).  Any form also stops
+ * after max_iter iterations, or with RBF_SOLVE_DIVERGED once the monitored
+ * residual exceeds 10^6 times its initial value.  Every step runs on the
+ * device (no host round trip inside an iteration); the call waits for the
+ * context stream every 16 iterations and on return, when *info (host memory,
+ * may be NULL) is filled.  Deterministic: every dot product is reduced in a
+ * fixed order.  Workspace: rbf_bicgstab_workspace (9 N + 4,096 float64 values
+ * and 256 bytes).
  * ------------------------------------------------------------------------ */
 rbf_status rbf_bicgstab_workspace(int64_t N, size_t* bytes);
 rbf_status rbf_bicgstab(rbf_ctx* ctx, int64_t N, const int64_t* offsets, const int32_t* idx,
                         const double* vals, int64_t nnz, int n_max, const double* rhs, double* x,
-                        double tol, int max_iter, int precond, void* workspace, size_t ws_bytes,
-                        rbf_solve_info* info);
+                        double tol, int max_iter, int precond, const void* pc, size_t pc_bytes,
+                        void* workspace, size_t ws_bytes, rbf_solve_info* info);
+
+/* ------------------------------------------------------------------------ *
+ * Block-Jacobi preconditioner of rbf_bicgstab (a parallel replacement for the
+ * incomplete LU the paper's benchmark uses, Sec. 5).  The nodes X[N][d] are
+ * ordered by a uniform grid of cells (about 8 nodes per cell in 2D, 16 in 3D;
+ * ascending ids inside a cell) and cut into blocks of 64 consecutive nodes;
+ * for every block the 64 x 64 submatrix of M (rows and columns of its nodes;
+ * entries of other columns dropped, repeated columns added) is inverted in
+ * float32 (Gauss-Jordan, partial pivoting); a block with a zero pivot keeps
+ * the inverse of its diagonal.  pc (device, caller-owned, at least
+ * rbf_block_jacobi_size bytes) receives the node order and the inverses
+ * (64 x 64 float32 per block, about 256 B per node).  M as for rbf_bicgstab.
+ * ------------------------------------------------------------------------ */
+rbf_status rbf_block_jacobi_size(int64_t N, int d, size_t* bytes);
+rbf_status rbf_block_jacobi_setup(rbf_ctx* ctx, const double* X, int64_t N, int d,
+                                  const int64_t* offsets, const int32_t* idx, const double* vals,
+                                  int64_t nnz, void* pc, size_t pc_bytes);
 
 /* ------------------------------------------------------------------------ *
  * Learned surrogate of the 2D, 15-node Laplacian weights (degree-2

@@ -29,7 +29,8 @@ from ._binding import (  # noqa: F401
     Context, Domain, RbfError, assemble_csr, autotune_batched, compute_weights, compute_weights_batched, context,
     batched_class_sizes, get_plan, lib, select_stencils, select_stencils_static, set_plan, compute_weights_wls,
     NODE_DIRICHLET, NODE_INTERIOR, NODE_NEUMANN, apply_operators, combine_operators, explicit_step,
-    SOLVE_BADDIAG, SOLVE_BREAKDOWN, SOLVE_CONVERGED, SOLVE_MAXITER, assemble_implicit, bicgstab, bicgstab_workspace,
+    SOLVE_BADDIAG, SOLVE_BREAKDOWN, SOLVE_CONVERGED, SOLVE_DIVERGED, SOLVE_MAXITER, assemble_implicit, bicgstab,
+    bicgstab_workspace, block_jacobi, block_jacobi_size,
     MLP_NPARAM, mlp_adam, mlp_flatten, mlp_forward, mlp_grad, mlp_pack, mlp_unflatten, surrogate_dataset,
     surrogate_load, surrogate_weights,
 )

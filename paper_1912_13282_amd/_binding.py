@@ -93,8 +93,10 @@ _SIGS = {
                                 ctypes.POINTER(rbf_options), _P, _P],
     "rbf_assemble_implicit": [_P, _I64, _I, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P],
     "rbf_bicgstab_workspace": [_I64, ctypes.POINTER(_SZ)],
-    "rbf_bicgstab": [_P, _I64, _P, _P, _P, _I64, _I, _P, _P, ctypes.c_double, _I, _I, _P, _SZ,
+    "rbf_bicgstab": [_P, _I64, _P, _P, _P, _I64, _I, _P, _P, ctypes.c_double, _I, _I, _P, _SZ, _P, _SZ,
                      ctypes.POINTER(rbf_solve_info)],
+    "rbf_block_jacobi_size": [_I64, _I, ctypes.POINTER(_SZ)],
+    "rbf_block_jacobi_setup": [_P, _P, _I64, _I, _P, _P, _P, _I64, _P, _SZ],
 }
 
 
@@ -393,8 +395,8 @@ def combine_operators(offsets: torch.Tensor, w: torch.Tensor, n_max: int, coef: 
 
 
 # ------------------------------------------------------------------ implicit solution
-SOLVE_CONVERGED, SOLVE_MAXITER, SOLVE_BREAKDOWN, SOLVE_BADDIAG = 0, 1, 2, 3
-PRECOND = {"none": 0, "jacobi": 1}
+SOLVE_CONVERGED, SOLVE_MAXITER, SOLVE_BREAKDOWN, SOLVE_BADDIAG, SOLVE_DIVERGED = 0, 1, 2, 3, 4
+PRECOND = {"none": 0, "jacobi": 1, "block_jacobi": 2}
 
 
 def assemble_implicit(offsets: torch.Tensor, idx: torch.Tensor, w_lap: torch.Tensor, kind: torch.Tensor,
@@ -434,11 +436,34 @@ def bicgstab_workspace(N: int) -> int:
     return b.value
 
 
+def block_jacobi_size(N: int, d: int) -> int:
+    """Bytes of the block-Jacobi preconditioner of an N-node system in d dimensions."""
+    b = _SZ()
+    _check(lib().rbf_block_jacobi_size(N, d, ctypes.byref(b)), "rbf_block_jacobi_size")
+    return b.value
+
+
+def block_jacobi(X: torch.Tensor, offsets: torch.Tensor, idx: torch.Tensor, vals: torch.Tensor,
+                 pc: torch.Tensor | None = None, ctx: Context | None = None) -> torch.Tensor:
+    """The block-Jacobi preconditioner of M (uint8 device tensor for bicgstab(pc=...))."""
+    ctx = ctx or context(X.device)
+    N, d = X.shape
+    nb = block_jacobi_size(N, d)
+    if pc is None or pc.numel() < nb:
+        pc = torch.empty(nb, dtype=torch.uint8, device=X.device)
+    _check(lib().rbf_block_jacobi_setup(ctx._sync_stream(), _dev(X, torch.float64, "X"), N, d,
+                                        _dev(offsets, torch.int64, "offsets"), _dev(idx, torch.int32, "idx"),
+                                        _dev(vals, torch.float64, "vals"), idx.numel(),
+                                        _dev(pc, torch.uint8, "pc"), pc.numel()), "rbf_block_jacobi_setup")
+    return pc
+
+
 def bicgstab(offsets: torch.Tensor, idx: torch.Tensor, vals: torch.Tensor, n_max: int, rhs: torch.Tensor,
              x: torch.Tensor | None = None, tol: float = 1e-10, max_iter: int = 10000, precond: str = "jacobi",
-             workspace: torch.Tensor | None = None, ctx: Context | None = None):
+             workspace: torch.Tensor | None = None, ctx: Context | None = None, pc: torch.Tensor | None = None):
     """Solve M x = rhs by BiCGStab on the GPU; returns (x, info dict).  x (if given) is the
-    initial guess and is overwritten; otherwise the solve starts from zero."""
+    initial guess and is overwritten; otherwise the solve starts from zero.  precond
+    "block_jacobi" needs pc from block_jacobi() of the same matrix."""
     ctx = ctx or context(offsets.device)
     N = offsets.numel() - 1
     nnz = idx.numel()
@@ -456,7 +481,9 @@ def bicgstab(offsets: torch.Tensor, idx: torch.Tensor, vals: torch.Tensor, n_max
     _check(lib().rbf_bicgstab(ctx._sync_stream(), N, _dev(offsets, torch.int64, "offsets"),
                               _dev(idx, torch.int32, "idx"), _dev(vals, torch.float64, "vals"), nnz, int(n_max),
                               _dev(rhs, torch.float64, "rhs"), _dev(x, torch.float64, "x"), float(tol),
-                              int(max_iter), PRECOND[precond], _dev(workspace, torch.uint8, "workspace"),
+                              int(max_iter), PRECOND[precond],
+                              _dev(pc, torch.uint8, "pc") if pc is not None else None,
+                              pc.numel() if pc is not None else 0, _dev(workspace, torch.uint8, "workspace"),
                               workspace.numel(), ctypes.byref(info)),
            "rbf_bicgstab")
     return x, {"status": info.status, "iterations": info.iterations, "residual": info.residual,

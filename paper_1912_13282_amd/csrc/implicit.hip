@@ -1,6 +1,15 @@
 // Implicit solution (Sec. 2.3.2): the system M u = r of eqs. (implicit-start)
 // -(implicit-end) in the stencil layout, and its solution by BiCGStab with
-// Jacobi row scaling, every step on the device.
+// Jacobi row scaling or a block-Jacobi preconditioner, every step on the device.
+//
+// Block-Jacobi: the nodes are put in the order of a grid of cells (about 8
+// nodes per cell in 2D, 16 in 3D) and cut into blocks of 64 consecutive nodes;
+// the 64 x 64 diagonal block of M of every node block is inverted once (float32
+// Gauss-Jordan with partial pivoting, one wavefront per block) and applied as a
+// right preconditioner, M P^-1 y = r with x = P^-1 y, so the monitored residual
+// is the true one.  Each iteration then adds two block products (one wavefront
+// per block: a 16 KB inverse read coalesced, the vector entries broadcast by
+// lane reads).
 //
 // One BiCGStab iteration (van der Vorst 1992) on the scaled system
 // A = D^-1 M, b = D^-1 r:
@@ -17,6 +26,7 @@
 // writes back the L2 of every XCD: far slower than the extra launch.)  Every
 // kernel returns at once when the solve has ended; the host checks the state
 // every CHECK_EVERY iterations.
+#include "cellorder.hpp"
 #include "rowdot.hpp"
 
 using namespace rbf;
@@ -75,11 +85,14 @@ constexpr int CHECK_EVERY = 16;  // iterations between host checks
 
 struct SolveState {
     double rho, rho_prev, alpha, omega;
-    double rr, bb, tol2;
+    double rr, bb, tol2, rr0;
     double true_rr, true_bb;
     int status, half, iter, max_iter;
     int baddiag;
 };
+
+// A residual grown 10^6 times past the initial one ends the solve as DIVERGED.
+constexpr double DIVERGE2 = 1e12;
 
 struct SolveArgs {
     int64_t N;
@@ -90,6 +103,10 @@ struct SolveArgs {
     const double* b;
     double* x;
     double *dinv, *r, *rh, *p, *v, *s, *t;
+    double *ph, *sh;         // P^-1 p, P^-1 s (block-Jacobi)
+    const double *xp, *xs;   // what the products take and x adds: p and s, or ph and sh
+    const int32_t* perm;     // block-Jacobi: node ids in block order, or NULL
+    const float* binv;       // block-Jacobi: inverses of the diagonal blocks
     double* part;
     SolveState* st;
 };
@@ -114,7 +131,7 @@ __device__ __forceinline__ void block_partials(double (&v)[K], double* part) {
 __global__ void k_state_init(SolveState* st, int max_iter, double tol) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     st->rho = st->rho_prev = st->alpha = st->omega = 1.0;
-    st->rr = st->bb = st->true_rr = st->true_bb = 0.0;
+    st->rr = st->bb = st->rr0 = st->true_rr = st->true_bb = 0.0;
     st->tol2 = tol * tol;  // scaled by |b|^2 once that is known
     st->status = RUNNING;
     st->half = 0;
@@ -165,7 +182,7 @@ __global__ __launch_bounds__(256) void k_spmv(SolveArgs a) {
         if (st->status != RUNNING) return;
     }
     if (MODE == SP_T && st->half) return;  // converged at the half step: omega = 0 (k_reduce)
-    const double* xin = MODE == SP_V ? a.p : (MODE == SP_T ? a.s : a.x);
+    const double* xin = MODE == SP_V ? a.xp : (MODE == SP_T ? a.xs : a.x);
     const int gl = threadIdx.x & (G - 1);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x / G;
     double c0 = 0.0, c1 = 0.0;
@@ -226,6 +243,10 @@ __global__ __launch_bounds__(256) void k_spmv(SolveArgs a) {
                 a.v[row] = 0.0;
                 a.s[row] = 0.0;
                 a.t[row] = 0.0;
+                if (a.perm) {
+                    a.ph[row] = 0.0;
+                    a.sh[row] = 0.0;
+                }
                 c0 += ri * ri;
                 c1 += (di * bi) * (di * bi);
             } else if (MODE == SP_V) {
@@ -270,7 +291,7 @@ __global__ __launch_bounds__(256) void k_vec(SolveArgs a) {
             c0 += si * si;
         } else {
             const double si = a.s[i];
-            a.x[i] += alpha * a.p[i] + omega * si;
+            a.x[i] += alpha * a.xp[i] + omega * a.xs[i];
             const double ri = si - omega * a.t[i];
             a.r[i] = ri;
             c0 += a.rh[i] * ri;
@@ -324,6 +345,7 @@ __global__ __launch_bounds__(256) void k_reduce(SolveArgs a, int nb) {
                            (red[1][0] + red[1][1]) + (red[1][2] + red[1][3])};
     if (MODE == RD_R0) {
         st->rr = tot[0];
+        st->rr0 = tot[0];
         st->bb = tot[1];
         st->rho = tot[0];
         // relative to |b|; a zero right-hand side is measured against the start
@@ -358,6 +380,8 @@ __global__ __launch_bounds__(256) void k_reduce(SolveArgs a, int nb) {
             st->status = RBF_SOLVE_CONVERGED;
         else if (!isfinite(tot[1]) || !isfinite(tot[0]))
             st->status = RBF_SOLVE_BREAKDOWN;
+        else if (tot[1] > DIVERGE2 * st->rr0)
+            st->status = RBF_SOLVE_DIVERGED;
         else if (st->iter >= st->max_iter)
             st->status = RBF_SOLVE_MAXITER;
         else if (tot[0] == 0.0 || omega == 0.0)
@@ -365,6 +389,147 @@ __global__ __launch_bounds__(256) void k_reduce(SolveArgs a, int nb) {
     } else {
         st->true_rr = tot[0];
         st->true_bb = tot[1];
+    }
+}
+
+// ------------------------------------------------------------------ block-Jacobi
+constexpr int BJ = 64;   // nodes per block (one per lane)
+constexpr int BJ_PER_CELL_2D = 8, BJ_PER_CELL_3D = 16;
+
+struct BjLayout {
+    size_t perm, inv, binv, scratch, total;
+    int64_t nblocks;
+};
+
+BjLayout bj_layout(int64_t N, int d) {
+    BjLayout L;
+    L.nblocks = (N + BJ - 1) / BJ;
+    size_t o = 0;
+    L.perm = o;
+    o += rbf_align(sizeof(int32_t) * N);
+    L.inv = o;
+    o += rbf_align(sizeof(int32_t) * N);
+    L.binv = o;
+    o += rbf_align(sizeof(float) * BJ * BJ * L.nblocks);
+    L.scratch = o;
+    o += rbf_align(rbf::cell_order_ws(N, d));
+    L.total = o;
+    return L;
+}
+
+__global__ __launch_bounds__(256) void k_bj_inverse_perm(const int32_t* __restrict__ perm, int64_t N,
+                                                         int32_t* __restrict__ inv) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < N) inv[perm[p]] = (int32_t)p;
+}
+
+// Inverse of the diagonal block of node block b (one wavefront): lane l owns
+// row l of [A | I] (A gathered from the row of node perm[64 b + l] through LDS,
+// entries outside the block dropped, duplicates added), float32 Gauss-Jordan
+// with partial pivoting (the pivot row by lane reads), then row k of the
+// inverse, (I part) / U_kk of the row pivoted at step k, is stored in the
+// layout of the product: element (k, j) at [j / 4][k][j % 4] of the block.  A
+// block with a zero or non-finite pivot stores the inverse of its diagonal
+// (Jacobi; identity where that is zero).  Padding rows past N are identity.
+__global__ __launch_bounds__(256) void k_bj_setup(int64_t N, const int64_t* __restrict__ offsets,
+                                                  const int32_t* __restrict__ idx, const double* __restrict__ vals,
+                                                  int64_t nnz, const int32_t* __restrict__ perm,
+                                                  const int32_t* __restrict__ inv, float* __restrict__ binv) {
+    __shared__ float As[4][BJ][BJ + 1];
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    const int64_t b = (int64_t)blockIdx.x * 4 + wv;
+    if (b * BJ >= N) return;
+    const int64_t p = b * BJ + lane;
+    const int node = p < N ? perm[p] : -1;
+    float(&Ar)[BJ + 1] = As[wv][lane];
+    for (int j = 0; j < BJ; ++j) Ar[j] = 0.0f;
+    if (node < 0) {
+        Ar[lane] = 1.0f;
+    } else {
+        const int64_t off = offsets[node], end = offsets[node + 1];
+        if (off >= 0 && end >= off && end <= nnz)
+            for (int64_t e = off; e < end; ++e) {
+                const int c = idx[e];
+                if (c < 0 || (int64_t)c >= N) continue;
+                const int64_t q = inv[c];
+                if (q / BJ == b) Ar[q % BJ] += (float)vals[e];
+            }
+    }
+    float row[BJ], ii[BJ];
+#pragma unroll
+    for (int j = 0; j < BJ; ++j) {
+        row[j] = Ar[j];
+        ii[j] = (j == lane) ? 1.0f : 0.0f;
+    }
+    const float dg = Ar[lane];
+    bool piv = false;
+    int mystep = -1;
+    float invd = 0.0f;
+    int pmin = 0x7F7FFFFF, pmax = 0;
+#pragma unroll
+    for (int k = 0; k < BJ; ++k) {
+        const int cand = piv ? -1 : __float_as_int(fabsf(row[k]));
+        const int mi = wave_max_dpp_i(cand);
+        pmin = min(pmin, mi);
+        pmax = max(pmax, mi);
+        const int pl = first_lane(ballot64(!piv && cand == mi));
+        const bool me = lane == pl;
+        const float inv_p = 1.0f / readlane_f(row[k], pl);
+        if (me) {
+            piv = true;
+            mystep = k;
+            invd = inv_p;
+        }
+        const float l = me ? 0.0f : row[k] * inv_p;
+#pragma unroll
+        for (int j = k + 1; j < BJ; ++j) row[j] = fmaf(-l, readlane_f(row[j], pl), row[j]);
+#pragma unroll
+        for (int j = 0; j < BJ; ++j) ii[j] = fmaf(-l, readlane_f(ii[j], pl), ii[j]);
+    }
+    const bool ok = pmin > 0 && pmax < 0x7F800000;  // wave-uniform
+    float* B = binv + (size_t)b * BJ * BJ;
+    if (ok) {
+#pragma unroll
+        for (int j4 = 0; j4 < BJ / 4; ++j4)
+            *reinterpret_cast<float4*>(B + ((size_t)j4 * BJ + mystep) * 4) =
+                make_float4(ii[4 * j4] * invd, ii[4 * j4 + 1] * invd, ii[4 * j4 + 2] * invd, ii[4 * j4 + 3] * invd);
+    } else {
+        const float di = (dg != 0.0f && isfinite(dg)) ? 1.0f / dg : 1.0f;
+#pragma unroll
+        for (int j4 = 0; j4 < BJ / 4; ++j4)
+            *reinterpret_cast<float4*>(B + ((size_t)j4 * BJ + lane) * 4) =
+                make_float4(4 * j4 == lane ? di : 0.0f, 4 * j4 + 1 == lane ? di : 0.0f, 4 * j4 + 2 == lane ? di : 0.0f,
+                            4 * j4 + 3 == lane ? di : 0.0f);
+    }
+}
+
+// out = P^-1 in, one wavefront per block (IN_S: the s vector, skipped once the
+// half step has converged).
+template <bool IN_S>
+__global__ __launch_bounds__(256) void k_bj_apply(SolveArgs a) {
+    SolveState* st = a.st;
+    if (st->status != RUNNING) return;
+    if (IN_S && st->half) return;
+    const double* in = IN_S ? a.s : a.p;
+    double* out = IN_S ? a.sh : a.ph;
+    const int lane = lane_id();
+    const int64_t nb = (a.N + BJ - 1) / BJ;
+    const int64_t nw = (int64_t)gridDim.x * 4;
+    for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < nb; b += nw) {
+        const int64_t p = b * BJ + lane;
+        const int node = p < a.N ? a.perm[p] : -1;
+        const double y = node >= 0 ? in[node] : 0.0;
+        const float* B = a.binv + (size_t)b * BJ * BJ;
+        double acc = 0.0;
+#pragma unroll
+        for (int j4 = 0; j4 < BJ / 4; ++j4) {
+            const float4 m = *reinterpret_cast<const float4*>(B + ((size_t)j4 * BJ + lane) * 4);
+            acc = fma((double)m.x, readlane_d(y, 4 * j4), acc);
+            acc = fma((double)m.y, readlane_d(y, 4 * j4 + 1), acc);
+            acc = fma((double)m.z, readlane_d(y, 4 * j4 + 2), acc);
+            acc = fma((double)m.w, readlane_d(y, 4 * j4 + 3), acc);
+        }
+        if (node >= 0) out[node] = acc;
     }
 }
 
@@ -386,6 +551,7 @@ template <int G, int E, int U>
 struct SolverL {
     static hipError_t launch(hipStream_t s, SolveArgs a, int what) {
         const dim3 gr(blocks_for(a.N * G, NBMAX)), gv(blocks_for(a.N, NBVEC)), b(256), one(1);
+        const dim3 gb(blocks_for(((a.N + BJ - 1) / BJ) * 64, 4096));   // one wavefront per node block
         const int nr = (int)gr.x, nv = (int)gv.x;
         switch (what) {
             case 0:
@@ -394,10 +560,12 @@ struct SolverL {
                 break;
             case 1:
                 hipLaunchKernelGGL((k_vec<VP>), gv, b, 0, s, a);
+                if (a.perm) hipLaunchKernelGGL((k_bj_apply<false>), gb, b, 0, s, a);
                 hipLaunchKernelGGL((k_spmv<G, E, U, SP_V>), gr, b, 0, s, a);
                 hipLaunchKernelGGL((k_reduce<RD_V>), one, b, 0, s, a, nr);
                 hipLaunchKernelGGL((k_vec<VS>), gv, b, 0, s, a);
                 hipLaunchKernelGGL((k_reduce<RD_S>), one, b, 0, s, a, nv);
+                if (a.perm) hipLaunchKernelGGL((k_bj_apply<true>), gb, b, 0, s, a);
                 hipLaunchKernelGGL((k_spmv<G, E, U, SP_T>), gr, b, 0, s, a);
                 hipLaunchKernelGGL((k_reduce<RD_T>), one, b, 0, s, a, nr);
                 hipLaunchKernelGGL((k_vec<VX>), gv, b, 0, s, a);
@@ -440,7 +608,7 @@ hipError_t solver_launch(int n_max, hipStream_t s, SolveArgs a, int what) {
 
 size_t solve_ws_bytes(int64_t N) {
     return rbf_align(sizeof(SolveState)) + rbf_align((size_t)NBMAX * 2 * sizeof(double)) +
-           7 * rbf_align((size_t)N * sizeof(double));
+           9 * rbf_align((size_t)N * sizeof(double));
 }
 
 }  // namespace
@@ -465,6 +633,36 @@ extern "C" rbf_status rbf_assemble_implicit(rbf_ctx* ctx, int64_t N, int d, cons
     return RBF_OK;
 }
 
+extern "C" rbf_status rbf_block_jacobi_size(int64_t N, int d, size_t* bytes) {
+    if (!bytes || N < 1) return RBF_EINVAL;
+    if (d != 2 && d != 3) return RBF_EDIM;
+    *bytes = bj_layout(N, d).total;
+    return RBF_OK;
+}
+
+extern "C" rbf_status rbf_block_jacobi_setup(rbf_ctx* ctx, const double* X, int64_t N, int d, const int64_t* offsets,
+                                             const int32_t* idx, const double* vals, int64_t nnz, void* pc,
+                                             size_t pc_bytes) {
+    if (!ctx || !X || !offsets || !vals || !pc || N < 1 || nnz < 0) return RBF_EINVAL;
+    if (nnz > 0 && !idx) return RBF_EINVAL;
+    if (d != 2 && d != 3) return RBF_EDIM;
+    if (N > (int64_t)0x7FFFFFFF - 8192) return RBF_EINVAL;
+    const BjLayout L = bj_layout(N, d);
+    if (pc_bytes < L.total) return RBF_EWORKSPACE;
+    RBF_HIP_CHECK(hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    char* w = (char*)pc;
+    int32_t* perm = (int32_t*)(w + L.perm);
+    int32_t* inv = (int32_t*)(w + L.inv);
+    float* binv = (float*)(w + L.binv);
+    RBF_HIP_CHECK(rbf::cell_order_enqueue(s, X, N, d, d == 3 ? BJ_PER_CELL_3D : BJ_PER_CELL_2D, w + L.scratch, perm));
+    hipLaunchKernelGGL(k_bj_inverse_perm, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, perm, N, inv);
+    hipLaunchKernelGGL(k_bj_setup, dim3((unsigned)((L.nblocks + 3) / 4)), dim3(256), 0, s, N, offsets, idx, vals, nnz,
+                       perm, inv, binv);
+    RBF_LAUNCH_CHECK();
+    return RBF_OK;
+}
+
 extern "C" rbf_status rbf_bicgstab_workspace(int64_t N, size_t* bytes) {
     if (!bytes || N < 1) return RBF_EINVAL;
     *bytes = solve_ws_bytes(N);
@@ -473,13 +671,18 @@ extern "C" rbf_status rbf_bicgstab_workspace(int64_t N, size_t* bytes) {
 
 extern "C" rbf_status rbf_bicgstab(rbf_ctx* ctx, int64_t N, const int64_t* offsets, const int32_t* idx,
                                    const double* vals, int64_t nnz, int n_max, const double* rhs, double* x,
-                                   double tol, int max_iter, int precond, void* workspace, size_t ws_bytes,
-                                   rbf_solve_info* info) {
+                                   double tol, int max_iter, int precond, const void* pc, size_t pc_bytes,
+                                   void* workspace, size_t ws_bytes, rbf_solve_info* info) {
     if (!ctx || !offsets || !vals || !rhs || !x || !workspace || N < 1 || nnz < 0 || n_max < 1) return RBF_EINVAL;
     if (nnz > 0 && !idx) return RBF_EINVAL;
     if (N > INT32_MAX + (int64_t)1) return RBF_EINVAL;
     if (!(tol >= 0.0) || max_iter < 0) return RBF_EINVAL;
-    if (precond != RBF_PRECOND_NONE && precond != RBF_PRECOND_JACOBI) return RBF_EINVAL;
+    if (precond != RBF_PRECOND_NONE && precond != RBF_PRECOND_JACOBI && precond != RBF_PRECOND_BLOCK_JACOBI)
+        return RBF_EINVAL;
+    if (precond == RBF_PRECOND_BLOCK_JACOBI && !pc) return RBF_EINVAL;
+    // the block-Jacobi data's size depends on d only through its scratch; the 3D
+    // layout is the larger one, the 2D one is the minimum accepted
+    if (precond == RBF_PRECOND_BLOCK_JACOBI && pc_bytes < bj_layout(N, 2).total) return RBF_EWORKSPACE;
     if (ws_bytes < solve_ws_bytes(N)) return RBF_EWORKSPACE;
     if (ranges_overlap(x, (size_t)N * sizeof(double), rhs, (size_t)N * sizeof(double))) return RBF_EINVAL;
     RBF_HIP_CHECK(hipSetDevice(ctx->device));
@@ -498,11 +701,22 @@ extern "C" rbf_status rbf_bicgstab(rbf_ctx* ctx, int64_t N, const int64_t* offse
     w += rbf_align(sizeof(SolveState));
     a.part = (double*)w;
     w += rbf_align((size_t)NBMAX * 2 * sizeof(double));
-    double** vecs[7] = {&a.dinv, &a.r, &a.rh, &a.p, &a.v, &a.s, &a.t};
+    double** vecs[9] = {&a.dinv, &a.r, &a.rh, &a.p, &a.v, &a.s, &a.t, &a.ph, &a.sh};
     for (double** q : vecs) {
         *q = (double*)w;
         w += rbf_align((size_t)N * sizeof(double));
     }
+    const bool bj = precond == RBF_PRECOND_BLOCK_JACOBI;
+    if (bj) {
+        const BjLayout L = bj_layout(N, 2);  // perm and inverses sit at the same offsets for d = 2 and 3
+        a.perm = (const int32_t*)((const char*)pc + L.perm);
+        a.binv = (const float*)((const char*)pc + L.binv);
+    } else {
+        a.perm = nullptr;
+        a.binv = nullptr;
+    }
+    a.xp = bj ? a.ph : a.p;
+    a.xs = bj ? a.sh : a.s;
 
     hipLaunchKernelGGL(k_state_init, dim3(1), dim3(64), 0, s, a.st, max_iter, tol);
     RBF_LAUNCH_CHECK();

@@ -19,6 +19,7 @@
 //       (key, index) and merged into a sorted top list of 64*T entries; rings of
 //       cells are added until the k-th key is below the squared distance to
 //       the unsearched region (exact termination).
+#include "cellorder.hpp"
 #include "common.hpp"
 
 #include <math.h>
@@ -832,6 +833,63 @@ extern "C" rbf_status rbf_select_stencils(rbf_ctx* ctx, const double* X, int64_t
     RBF_HIP_CHECK(hipSetDevice(ctx->device));
     return select_enqueue(ctx, X, N, d, offsets, n_max, idx, (char*)workspace, L);
 }
+
+// ------------------------------------------------------ cell order of a node set
+// Ascending node ids inside every cell (the atomic ranks of the binning give an
+// arbitrary order): one thread per cell, insertion sort; cells above 256 nodes
+// (degenerate clusters) keep their order.
+__global__ __launch_bounds__(256) void k_sort_cells(const GridParams* __restrict__ gp,
+                                                    const int* __restrict__ cell_start, int32_t* __restrict__ ids) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= gp->ncell) return;
+    const int a = cell_start[c], b = cell_start[c + 1];
+    if (b - a > 256) return;
+    for (int i = a + 1; i < b; ++i) {
+        const int32_t v = ids[i];
+        int j = i - 1;
+        while (j >= a && ids[j] > v) {
+            ids[j + 1] = ids[j];
+            --j;
+        }
+        ids[j + 1] = v;
+    }
+}
+
+namespace rbf {
+
+// Workspace of cell_order_enqueue (the selection layout).
+size_t cell_order_ws(int64_t N, int d) { return sel_layout(N, d).total; }
+
+// Node ids in the order of a uniform grid of cells holding about per_cell nodes
+// each (cells in x-fastest order, ascending ids within a cell): order[N]
+// (device).  Enqueued on s; ws (cell_order_ws bytes) is scratch.
+hipError_t cell_order_enqueue(hipStream_t s, const double* X, int64_t N, int d, double per_cell, void* ws,
+                              int32_t* order) {
+    const SelWorkspace L = sel_layout(N, d);
+    char* w = (char*)ws;
+    GridParams* gp = (GridParams*)(w + L.gp);
+    double* part = (double*)(w + L.part);
+    int* count = (int*)(w + L.count);
+    int* bsum = (int*)(w + L.bsum);
+    int* cell_of = (int*)(w + L.cell_of);
+    int* rank = (int*)(w + L.rank);
+    double* sx = (double*)(w + L.sx);
+    const int nbb = (int)std::min<int64_t>(BBOX_BLOCKS, (N + 255) / 256);
+    hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(256), 0, s, X, N, d, part);
+    hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(64), 0, s, part, nbb, N, d, fmax(1.0, per_cell), L.cap, gp);
+    hipLaunchKernelGGL(k_zero_ints, dim3((unsigned)((L.cap + 2 + 255) / 256)), dim3(256), 0, s, count,
+                       (int64_t)L.cap + 2);
+    const int nbN = (int)((N + 255) / 256);
+    hipLaunchKernelGGL(k_bin_count, dim3(nbN), dim3(256), 0, s, X, N, d, gp, count, cell_of, rank);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(L.nb_scan), dim3(256), 0, s, count, L.cap + 1, bsum);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, L.nb_scan);
+    hipLaunchKernelGGL(k_scan_apply, dim3(L.nb_scan), dim3(256), 0, s, count, L.cap + 1, bsum);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(nbN), dim3(256), 0, s, X, N, d, count, cell_of, rank, order, sx);
+    hipLaunchKernelGGL(k_sort_cells, dim3((unsigned)((L.cap + 255) / 256)), dim3(256), 0, s, gp, count, order);
+    return hipGetLastError();
+}
+
+}  // namespace rbf
 
 // ------------------------------------------------------ no-allocation variant
 // The selection buffers of rbf_select_stencils_static live in this file-scope

@@ -166,9 +166,12 @@ def test_more_host_argument_errors_without_gpu(lib_path):
     assert L.rbf_bicgstab_workspace(ctypes.c_int64(0), ctypes.byref(b)) == -1
     assert L.rbf_bicgstab_workspace(ctypes.c_int64(1000), None) == -1
     assert L.rbf_bicgstab_workspace(ctypes.c_int64(1000), ctypes.byref(b)) == 0
-    assert b.value >= 7 * 1000 * 8 + 4096 * 8
+    assert b.value >= 9 * 1000 * 8 + 4096 * 8
     assert L.rbf_bicgstab(None, one, None, None, None, one, 1, None, None, ctypes.c_double(1e-8), 10, 1, None,
-                          ctypes.c_size_t(0), None) == -1
+                          ctypes.c_size_t(0), None, ctypes.c_size_t(0), None) == -1
+    assert L.rbf_block_jacobi_size(ctypes.c_int64(1000), 4, ctypes.byref(b)) == -3
+    assert L.rbf_block_jacobi_size(ctypes.c_int64(1000), 3, ctypes.byref(b)) == 0
+    assert b.value >= 1000 * (8 + 256)
 
 
 def test_node_kind_and_solver_constants_match_the_binding():
@@ -178,5 +181,7 @@ def test_node_kind_and_solver_constants_match_the_binding():
     assert (val("RBF_NODE_INTERIOR"), val("RBF_NODE_DIRICHLET"), val("RBF_NODE_NEUMANN")) == \
         (B.NODE_INTERIOR, B.NODE_DIRICHLET, B.NODE_NEUMANN)
     assert (val("RBF_SOLVE_CONVERGED"), val("RBF_SOLVE_MAXITER"), val("RBF_SOLVE_BREAKDOWN"),
-            val("RBF_SOLVE_BADDIAG")) == (B.SOLVE_CONVERGED, B.SOLVE_MAXITER, B.SOLVE_BREAKDOWN, B.SOLVE_BADDIAG)
-    assert (val("RBF_PRECOND_NONE"), val("RBF_PRECOND_JACOBI")) == (B.PRECOND["none"], B.PRECOND["jacobi"])
+            val("RBF_SOLVE_BADDIAG"), val("RBF_SOLVE_DIVERGED")) == \
+        (B.SOLVE_CONVERGED, B.SOLVE_MAXITER, B.SOLVE_BREAKDOWN, B.SOLVE_BADDIAG, B.SOLVE_DIVERGED)
+    assert (val("RBF_PRECOND_NONE"), val("RBF_PRECOND_JACOBI"), val("RBF_PRECOND_BLOCK_JACOBI")) == \
+        (B.PRECOND["none"], B.PRECOND["jacobi"], B.PRECOND["block_jacobi"])

@@ -112,7 +112,8 @@ def _scaled_residual(off, idx, vals, rhs, x, jacobi=True):
 # 2D with Neumann rows needs the Jacobi scaling (about 4,200 iterations here);
 # the Dirichlet problems converge in a few hundred either way
 @pytest.mark.parametrize("d,precond,neumann", [(2, "jacobi", True), (2, "none", False), (3, "jacobi", False),
-                                               (3, "none", False)])
+                                               (3, "none", False), (2, "block_jacobi", True),
+                                               (3, "block_jacobi", False)])
 def test_bicgstab_parity_with_direct_solve(gpu, d, precond, neumann):
     rb = _rb()
     nd, kind, normals, off, idx, W, f, g, u0 = _annulus_problem(0.025 if d == 2 else 0.12, d=d,
@@ -121,13 +122,17 @@ def test_bicgstab_parity_with_direct_solve(gpu, d, precond, neumann):
     ud = implicit.solve(off, idx, vals, rhs)
     tol = 1e-12
     n_max = int(np.diff(off).max())
+    pc = rb.block_jacobi(_t(nd.X, gpu), _t(off, gpu), _t(idx, gpu), _t(vals, gpu)) if precond == "block_jacobi" \
+        else None
     x, info = rb.bicgstab(_t(off, gpu), _t(idx, gpu), _t(vals, gpu), n_max, _t(rhs, gpu), tol=tol, max_iter=20000,
-                          precond=precond)
+                          precond=precond, pc=pc)
     assert info["status"] == rb.SOLVE_CONVERGED, info
     xh = x.cpu().numpy()
-    # the monitored (recursively updated) residual and the true one agree to rounding
+    # the monitored (recursively updated) residual and the true one agree to rounding;
+    # over the thousand-odd iterations of the Neumann problem the recursion drifts
+    # further from b - M x at this tolerance (the true residual is reported in info)
     res = _scaled_residual(off, idx, vals, rhs, xh, jacobi=precond == "jacobi")
-    assert res <= 10 * tol, (res, info)
+    assert res <= (30 if precond == "block_jacobi" else 10) * tol, (res, info)
     assert info["residual"] <= tol
     M = implicit.matrix(off, idx, vals)
     # the unscaled residual recomputed on the host, to the rounding of forming r - M x
@@ -138,10 +143,52 @@ def test_bicgstab_parity_with_direct_solve(gpu, d, precond, neumann):
     # the direct solution, to the accuracy that residual allows (condition number below 1e5 here)
     assert np.abs(xh - ud).max() <= 1e5 * 10 * tol * np.abs(ud).max(), np.abs(xh - ud).max()
     assert np.abs(xh - u0).max() < 0.05
-    # deterministic: a second solve is bit-identical
+    # deterministic: a second solve (and a second preconditioner set-up) is bit-identical
+    if pc is not None:
+        pc = rb.block_jacobi(_t(nd.X, gpu), _t(off, gpu), _t(idx, gpu), _t(vals, gpu))
     x2, info2 = rb.bicgstab(_t(off, gpu), _t(idx, gpu), _t(vals, gpu), n_max, _t(rhs, gpu), tol=tol, max_iter=20000,
-                            precond=precond)
+                            precond=precond, pc=pc)
     assert torch.equal(x, x2) and info2["iterations"] == info["iterations"]
+    print(f"  {d}D {precond} neumann={neumann}: {info['iterations']} iterations", flush=True)
+
+
+@pytest.mark.parametrize("d,h,n", [(2, 0.01, 9), (3, 0.05, 35)])
+def test_block_jacobi_cuts_iterations(gpu, d, h, n):
+    """The Sec. 5 Dirichlet problem (degree 2): block-Jacobi BiCGStab converges to the
+    same solution as Jacobi in fewer iterations (2D: under 55% of Jacobi's; 3D, where
+    the 35-node stencils reach further out of a 64-node block: under 75%)."""
+    rb = _rb()
+    nd = ns.annulus(h, 1006, d=d)
+    off, idx = knn.knn_exact(nd.X, n)
+    W, _ = rbffd.weights(nd.X, off, idx, 2, ("lap",))
+    kind = np.where(nd.is_boundary, hc.DIRICHLET, hc.INTERIOR).astype(np.uint8)
+    vals, rhs = implicit.assemble(off, idx.astype(np.int32), W[0], None, kind, None, f=poisson.lap_u0(nd.X),
+                                  g=poisson.u0(nd.X))
+    T = [_t(a, gpu) for a in (off, idx.astype(np.int32), vals, rhs)]
+    xj, ij = rb.bicgstab(*T[:3], n, T[3], tol=1e-10, max_iter=20000, precond="jacobi")
+    pc = rb.block_jacobi(_t(nd.X, gpu), *T[:3])
+    xb, ib = rb.bicgstab(*T[:3], n, T[3], tol=1e-10, max_iter=20000, precond="block_jacobi", pc=pc)
+    print(f"  {d}D N={nd.N}: Jacobi {ij['iterations']} iterations, block-Jacobi {ib['iterations']}", flush=True)
+    assert ij["status"] == rb.SOLVE_CONVERGED and ib["status"] == rb.SOLVE_CONVERGED
+    assert ib["iterations"] <= (0.55 if d == 2 else 0.75) * ij["iterations"]
+    u0 = poisson.u0(nd.X)
+    ej, eb = np.abs(xj.cpu().numpy() - u0).max(), np.abs(xb.cpu().numpy() - u0).max()
+    assert abs(eb - ej) <= 1e-3 * ej
+
+
+def test_3d_neumann_reports_failure(gpu):
+    """Closest-node Neumann rows in 3D: a few percent have a normal-derivative weight
+    at the node of the wrong sign, the operator is unstable and no preconditioner
+    makes BiCGStab converge; the solver must say so (never report CONVERGED)."""
+    rb = _rb()
+    nd, kind, normals, off, idx, W, f, g, u0 = _annulus_problem(0.08, d=3, n=35, P=2, neumann=True)
+    vals, rhs = implicit.assemble(off, idx, W[0], W[1:], kind, normals, f=f, g=g)
+    T = [_t(a, gpu) for a in (off, idx, vals, rhs)]
+    for precond in ("jacobi", "block_jacobi"):
+        pc = rb.block_jacobi(_t(nd.X, gpu), *T[:3]) if precond == "block_jacobi" else None
+        x, info = rb.bicgstab(*T[:3], 35, T[3], tol=1e-10, max_iter=3000, precond=precond, pc=pc)
+        print(f"  {precond}: {info}", flush=True)
+        assert info["status"] in (rb.SOLVE_MAXITER, rb.SOLVE_DIVERGED, rb.SOLVE_BREAKDOWN)
 
 
 def test_bicgstab_csr_with_ragged_rows(gpu):
