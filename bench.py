@@ -135,8 +135,8 @@ def parse():
     ap.add_argument("--workload", default="cube_sphere3d", choices=["cube_sphere3d", "mixed", "learned", "large3d", "explicit", "poisson3d", "poisson2d", "wls",
                              "counters"])
     ap.add_argument("--form", default="f32_ir", choices=["f32_ir", "f64"])
-    ap.add_argument("--precond", default="block_jacobi", choices=["block_jacobi", "jacobi", "none"],
-                    help="poisson: BiCGStab preconditioner")
+    ap.add_argument("--precond", default="auto", choices=["auto", "block_jacobi", "jacobi", "none"],
+                    help="poisson: BiCGStab preconditioner (auto: block-Jacobi in 3D, Jacobi in 2D)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-compare", action="store_true", help="time only the reported form")
     ap.add_argument("--cpu-sample", type=int, default=None,
@@ -910,12 +910,12 @@ def bicgstab_bytes_per_row(n, precond="jacobi"):
     """Algorithmic HBM bytes per row of one BiCGStab iteration: two row products
     (row offset, n indices and values, the gathered vector once, the inverse
     diagonal, one dot operand, the result) and the three vector passes
-    (p: 3 reads + 1 write, s: 2 + 1, x and r: 5 + 2).  Block-Jacobi adds two
-    block products per row: 64 float32 entries of the inverse, the permutation
-    entry, the input and the output."""
+    (p: 3 reads + 1 write, s: 2 + 1, x and r: 5 + 2).  Block-Jacobi adds to the
+    p and s passes the block product of each row: 64 float16 entries of the
+    inverse, its float32 scale, the permutation entry and the output."""
     b = 2 * (8 + 12.0 * n + 8 + 8 + 8 + 8) + 8 * (4 + 3 + 7)
     if precond == "block_jacobi":
-        b += 2 * (64 * 4 + 4 + 8 + 8)
+        b += 2 * (64 * 2 + 4 + 4 + 8)
     return b
 
 
@@ -943,8 +943,14 @@ def bench_poisson(a, torch, rb, B):
     vals = torch.empty(nnz, dtype=torch.float64, device=dev)
     rhs = torch.empty(N, dtype=torch.float64, device=dev)
     x = torch.empty(N, dtype=torch.float64, device=dev)
-    sws = torch.empty(rb.bicgstab_workspace(N), dtype=torch.uint8, device=dev)
+    sws = torch.empty(rb.bicgstab_workspace(N, nnz, "block_jacobi"), dtype=torch.uint8, device=dev)  # the larger form
     tol = 1e-10
+    # auto: block-Jacobi where its block products are small against the row
+    # products (3D, 35 entries per row); with 9 entries per row (2D) the block
+    # products nearly double an iteration's bytes and the matrix no longer stays
+    # in the last-level cache, for a smaller cut in iterations
+    if a.precond == "auto":
+        a.precond = "block_jacobi" if d == 3 else "jacobi"
     bj = a.precond == "block_jacobi"
     pc = torch.empty(rb.block_jacobi_size(N, d), dtype=torch.uint8, device=dev)
     timer = Timer(torch, ["select_stencils", "compute_weights", "assemble_implicit", "precondition", "bicgstab"])
@@ -983,7 +989,7 @@ def bench_poisson(a, torch, rb, B):
     it = max(1, info["iterations"])
     per_row = bicgstab_bytes_per_row(n, a.precond)
     gbs = per_row * N * it / (ph["bicgstab"] / 1e3) / 1e9
-    solver = {"block_jacobi": "BiCGStab, block-Jacobi (64-node cell blocks, float32 inverses)",
+    solver = {"block_jacobi": "BiCGStab, block-Jacobi (64-node cell blocks, float16 inverses)",
               "jacobi": "BiCGStab, Jacobi row scaling", "none": "BiCGStab, unpreconditioned"}[a.precond]
     res = base_line(a, N / (ms / 1e3), ms, "f64",
                     {"workload": f"poisson_annulus_{d}d", "N": N, "nnz": nnz, "n": n, "degree": P, "ops": ["lap"],
@@ -991,12 +997,11 @@ def bench_poisson(a, torch, rb, B):
                      "step": "select_stencils + compute_weights + assemble_implicit + precondition + bicgstab"})
     res["metric"] = "Poisson nodes solved/s (stencils + weights + assembly + BiCGStab)"
     res["unit"] = "nodes/s"
-    bja = f"k_bj_apply<false>, " if bj else ""
-    bjs = f"k_bj_apply<true>, " if bj else ""
+    vp, vs = ("k_bj_vec<P>", "k_bj_vec<S>") if bj else ("k_vec<P>", "k_vec<S>")
     res["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                        "frac": gbs / PEAK_HBM_GBS, "traffic": recorded_traffic(a.workload),
-                       "kernel": f"BiCGStab iteration (k_vec<P>, {bja}k_spmv<8,{(n + 7) // 8},V>, k_vec<S>, "
-                                 f"{bjs}k_spmv<8,{(n + 7) // 8},T>, k_vec<X>)",
+                       "kernel": f"BiCGStab iteration ({vp}, k_spmv<V>, k_reduce, {vs}, k_spmv<T>, k_reduce, "
+                                 f"k_vec<X>, k_reduce; row products k_spmv<8,{(n + 7) // 8}>)",
                        "bytes_per_row_per_iteration": per_row, "rows": N, "iterations": it}
     if not a.no_compare:
         # the other preconditioner on the same system, one untimed-by-the-step solve

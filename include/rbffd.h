@@ -389,17 +389,20 @@ typedef struct rbf_solve_info {
  * D = I; both stop when ||D^-1 (r - M x)|| <= tol ||D^-1 r||.
  * RBF_PRECOND_BLOCK_JACOBI solves M P^-1 y = r, x = P^-1 y, with P the block
  * diagonal of M over the node blocks of rbf_block_jacobi_setup (pc, built from
- * the same M), and stops when ||r - M x|| <= tol ||r||.  pc/pc_bytes are
- * ignored by the other preconditioners (may be NULL).  Any form also stops
+ * the same M), and stops when ||r - M x|| <= tol ||r||; it copies M, r and x
+ * into the node order of pc inside the workspace (x is copied back on return),
+ * so its iterations read every vector contiguously.  pc/pc_bytes are ignored by
+ * the other preconditioners (may be NULL).  Any form also stops
  * after max_iter iterations, or with RBF_SOLVE_DIVERGED once the monitored
  * residual exceeds 10^6 times its initial value.  Every step runs on the
  * device (no host round trip inside an iteration); the call waits for the
  * context stream every 16 iterations and on return, when *info (host memory,
  * may be NULL) is filled.  Deterministic: every dot product is reduced in a
- * fixed order.  Workspace: rbf_bicgstab_workspace (9 N + 4,096 float64 values
- * and 256 bytes).
+ * fixed order.  Workspace: rbf_bicgstab_workspace for the same N, nnz and
+ * preconditioner (9 N + 6,144 float64 values and 256 bytes; block-Jacobi adds
+ * the copy of M, about 12 (nnz + N) + 24 N bytes).
  * ------------------------------------------------------------------------ */
-rbf_status rbf_bicgstab_workspace(int64_t N, size_t* bytes);
+rbf_status rbf_bicgstab_workspace(int64_t N, int64_t nnz, int precond, size_t* bytes);
 rbf_status rbf_bicgstab(rbf_ctx* ctx, int64_t N, const int64_t* offsets, const int32_t* idx,
                         const double* vals, int64_t nnz, int n_max, const double* rhs, double* x,
                         double tol, int max_iter, int precond, const void* pc, size_t pc_bytes,
@@ -414,8 +417,9 @@ rbf_status rbf_bicgstab(rbf_ctx* ctx, int64_t N, const int64_t* offsets, const i
  * entries of other columns dropped, repeated columns added) is inverted in
  * float32 (Gauss-Jordan, partial pivoting); a block with a zero pivot keeps
  * the inverse of its diagonal.  pc (device, caller-owned, at least
- * rbf_block_jacobi_size bytes) receives the node order and the inverses
- * (64 x 64 float32 per block, about 256 B per node).  M as for rbf_bicgstab.
+ * rbf_block_jacobi_size bytes) receives the node order and the inverses, each
+ * row stored as float16 divided by its largest magnitude with that scale in
+ * float32 (about 140 B per node).  M as for rbf_bicgstab.
  * ------------------------------------------------------------------------ */
 rbf_status rbf_block_jacobi_size(int64_t N, int d, size_t* bytes);
 rbf_status rbf_block_jacobi_setup(rbf_ctx* ctx, const double* X, int64_t N, int d,

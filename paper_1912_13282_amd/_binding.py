@@ -92,7 +92,7 @@ _SIGS = {
     "rbf_compute_weights_wls": [_P, _P, _I64, _I, _P, _P, _I64, _I, _I, _U, _I, ctypes.c_double,
                                 ctypes.POINTER(rbf_options), _P, _P],
     "rbf_assemble_implicit": [_P, _I64, _I, _P, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P],
-    "rbf_bicgstab_workspace": [_I64, ctypes.POINTER(_SZ)],
+    "rbf_bicgstab_workspace": [_I64, _I64, _I, ctypes.POINTER(_SZ)],
     "rbf_bicgstab": [_P, _I64, _P, _P, _P, _I64, _I, _P, _P, ctypes.c_double, _I, _I, _P, _SZ, _P, _SZ,
                      ctypes.POINTER(rbf_solve_info)],
     "rbf_block_jacobi_size": [_I64, _I, ctypes.POINTER(_SZ)],
@@ -430,9 +430,12 @@ def assemble_implicit(offsets: torch.Tensor, idx: torch.Tensor, w_lap: torch.Ten
     return vals, rhs
 
 
-def bicgstab_workspace(N: int) -> int:
+def bicgstab_workspace(N: int, nnz: int = 0, precond: str = "jacobi") -> int:
+    """Workspace bytes of bicgstab() for N rows, nnz stored entries and the preconditioner."""
+    if precond not in PRECOND:
+        raise RbfError(f"precond must be one of {sorted(PRECOND)}")
     b = ctypes.c_size_t()
-    _check(lib().rbf_bicgstab_workspace(N, ctypes.byref(b)), "rbf_bicgstab_workspace")
+    _check(lib().rbf_bicgstab_workspace(N, nnz, PRECOND[precond], ctypes.byref(b)), "rbf_bicgstab_workspace")
     return b.value
 
 
@@ -474,7 +477,7 @@ def bicgstab(offsets: torch.Tensor, idx: torch.Tensor, vals: torch.Tensor, n_max
     x = torch.zeros(N, dtype=torch.float64, device=offsets.device) if x is None else x
     if x.numel() != N:
         raise RbfError("x must have N entries")
-    ws_bytes = bicgstab_workspace(N)
+    ws_bytes = bicgstab_workspace(N, nnz, precond)
     if workspace is None or workspace.numel() < ws_bytes:
         workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=offsets.device)
     info = rbf_solve_info()

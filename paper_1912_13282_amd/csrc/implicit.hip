@@ -5,23 +5,29 @@
 // Block-Jacobi: the nodes are put in the order of a grid of cells (about 8
 // nodes per cell in 2D, 16 in 3D) and cut into blocks of 64 consecutive nodes;
 // the 64 x 64 diagonal block of M of every node block is inverted once (float32
-// Gauss-Jordan with partial pivoting, one wavefront per block) and applied as a
-// right preconditioner, M P^-1 y = r with x = P^-1 y, so the monitored residual
-// is the true one.  Each iteration then adds two block products (one wavefront
-// per block: a 16 KB inverse read coalesced, the vector entries broadcast by
-// lane reads).
+// Gauss-Jordan with partial pivoting, one wavefront per block), stored as
+// float16 rows scaled by their largest entry, and applied as a right
+// preconditioner, M P^-1 y = r with x = P^-1 y, so the monitored residual is the
+// true one.  The solve runs in block order: M (rows renumbered, columns mapped),
+// r and x are copied into that order in the workspace at the start and x is
+// copied back at the end, so every vector pass is contiguous and the row
+// products gather from spatially compact rows.  The block products are fused
+// into the p and s updates (one wavefront per block: an 8 KB inverse read
+// coalesced, the vector entries broadcast by lane reads).
 //
 // One BiCGStab iteration (van der Vorst 1992) on the scaled system
-// A = D^-1 M, b = D^-1 r:
-//     p = r + beta (p - omega v)          k_vec<P>      beta = (rho / rho_prev)(alpha / omega)
+// A = D^-1 M, b = D^-1 r (D = I for the block form, whose products take
+// ph = P^-1 p and sh = P^-1 s, and whose x adds them):
+//     p = r + beta (p - omega v)          k_vec<P> | k_bj_vec<P>    beta = (rho / rho_prev)(alpha / omega)
 //     v = A p,  alpha = rho / (rh . v)    k_spmv<V>
-//     s = r - alpha v,  |s|^2             k_vec<S>      |s| small: x += alpha p, done
-//     t = A s,  omega = (t . s)/(t . t)   k_spmv<T>
+//     s = r - alpha v,  |s|^2             k_vec<S> | k_bj_vec<S>
+//     t = A s,  omega = (t . s)/(t . t)   k_spmv<T>    |s| small: omega = 0, done after the x update
 //     x += alpha p + omega s,  r = s - omega t,  rho = rh . r,  |r|^2      k_vec<X>
 // The scalars live in device memory.  Each dot product is summed per block in
 // a fixed order; a one-block kernel then adds the block sums, again in a fixed
-// order, and updates the scalars (k_reduce), so no kernel waits for the host
-// and the result does not depend on timing.  (Letting the last block of the
+// order, and updates the scalars (k_reduce: after v, after t -- with |s|^2 --
+// and after x), so no kernel waits for the host and the result does not
+// depend on timing.  (Letting the last block of the
 // producing kernel do it would need a device-scope release per block, which
 // writes back the L2 of every XCD: far slower than the extra launch.)  Every
 // kernel returns at once when the solve has ended; the host checks the state
@@ -81,6 +87,7 @@ __global__ __launch_bounds__(256) void k_assemble(int64_t N, int d, const int64_
 constexpr int RUNNING = -1;
 constexpr int NBMAX = 2048;      // blocks of the row-product kernels (bounds the block sums)
 constexpr int NBVEC = 2048;      // blocks of the vector kernels
+static_assert(NBVEC <= NBMAX, "the vector kernels share the block sums of the row products");
 constexpr int CHECK_EVERY = 16;  // iterations between host checks
 
 struct SolveState {
@@ -105,9 +112,10 @@ struct SolveArgs {
     double *dinv, *r, *rh, *p, *v, *s, *t;
     double *ph, *sh;         // P^-1 p, P^-1 s (block-Jacobi)
     const double *xp, *xs;   // what the products take and x adds: p and s, or ph and sh
-    const int32_t* perm;     // block-Jacobi: node ids in block order, or NULL
-    const float* binv;       // block-Jacobi: inverses of the diagonal blocks
-    double* part;
+    const _Float16* binv;    // block-Jacobi (the system in block order): inverses, rows scaled, or NULL
+    const float* bscale;     // block-Jacobi: the row scales
+    double* part;            // block sums of the row products and of x (two per block)
+    double* part_s;          // block sums of |s|^2 (one per block)
     SolveState* st;
 };
 
@@ -181,7 +189,6 @@ __global__ __launch_bounds__(256) void k_spmv(SolveArgs a) {
     if (MODE == SP_V || MODE == SP_T) {
         if (st->status != RUNNING) return;
     }
-    if (MODE == SP_T && st->half) return;  // converged at the half step: omega = 0 (k_reduce)
     const double* xin = MODE == SP_V ? a.xp : (MODE == SP_T ? a.xs : a.x);
     const int gl = threadIdx.x & (G - 1);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x / G;
@@ -243,7 +250,7 @@ __global__ __launch_bounds__(256) void k_spmv(SolveArgs a) {
                 a.v[row] = 0.0;
                 a.s[row] = 0.0;
                 a.t[row] = 0.0;
-                if (a.perm) {
+                if (a.binv) {
                     a.ph[row] = 0.0;
                     a.sh[row] = 0.0;
                 }
@@ -272,7 +279,7 @@ __global__ __launch_bounds__(256) void k_spmv(SolveArgs a) {
 enum { VP, VS, VX };
 
 //   VP: p = r + beta (p - omega v)
-//   VS: s = r - alpha v;  |s|^2 (half-step convergence)
+//   VS: s = r - alpha v;  |s|^2 (half-step convergence, checked with omega)
 //   VX: x += alpha p + omega s;  r = s - omega t;  rho = rh . r, |r|^2
 template <int MODE>
 __global__ __launch_bounds__(256) void k_vec(SolveArgs a) {
@@ -292,57 +299,70 @@ __global__ __launch_bounds__(256) void k_vec(SolveArgs a) {
         } else {
             const double si = a.s[i];
             a.x[i] += alpha * a.xp[i] + omega * a.xs[i];
-            const double ri = si - omega * a.t[i];
+            const double ri = omega != 0.0 ? si - omega * a.t[i] : si;  // omega = 0: converged at s
             a.r[i] = ri;
             c0 += a.rh[i] * ri;
             c1 += ri * ri;
         }
     }
     if (MODE == VP) return;
-    double tot[2] = {c0, c1};
-    block_partials<2>(tot, a.part);
+    if (MODE == VS) {
+        double tot[1] = {c0};
+        block_partials<1>(tot, a.part_s);
+    } else {
+        double tot[2] = {c0, c1};
+        block_partials<2>(tot, a.part);
+    }
 }
 
-enum { RD_R0, RD_V, RD_S, RD_T, RD_X, RD_TRUE };
+enum { RD_R0, RD_V, RD_T, RD_X, RD_TRUE };
 
-// Sum of the nb block sums (fixed order) and the scalar update of each step.
-template <int MODE>
-__global__ __launch_bounds__(256) void k_reduce(SolveArgs a, int nb) {
-    SolveState* st = a.st;
-    if (MODE != RD_R0 && MODE != RD_TRUE && st->status != RUNNING) return;
-    if (MODE == RD_T && st->half) {
-        if (threadIdx.x == 0) st->omega = 0.0;
-        return;
-    }
-    __shared__ double red[2][4];
+// Sum of the nb block sums part[b][K] in a fixed order, by the whole block;
+// the totals are valid in thread 0.
+template <int K>
+__device__ __forceinline__ void sum_parts(const double* part, int nb, double (&tot)[K]) {
+    __shared__ double red[K][4];
     // eight independent accumulators per thread keep eight loads in flight;
     // they are combined in a fixed order
-    double q0[8], q1[8];
+    double q[K][8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) q0[k] = q1[k] = 0.0;
+    for (int c = 0; c < K; ++c)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) q[c][k] = 0.0;
     for (int b0 = threadIdx.x; b0 < nb; b0 += 8 * 256) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int b = b0 + k * 256;
-            if (b < nb) {
-                q0[k] += a.part[2 * b];
-                q1[k] += a.part[2 * b + 1];
-            }
+            if (b < nb)
+#pragma unroll
+                for (int c = 0; c < K; ++c) q[c][k] += part[K * b + c];
         }
     }
-    double s0 = ((q0[0] + q0[1]) + (q0[2] + q0[3])) + ((q0[4] + q0[5]) + (q0[6] + q0[7]));
-    double s1 = ((q1[0] + q1[1]) + (q1[2] + q1[3])) + ((q1[4] + q1[5]) + (q1[6] + q1[7]));
-    s0 = wave_sum_d(s0);
-    s1 = wave_sum_d(s1);
     const int wv = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        red[0][wv] = s0;
-        red[1][wv] = s1;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        double sc = ((q[c][0] + q[c][1]) + (q[c][2] + q[c][3])) + ((q[c][4] + q[c][5]) + (q[c][6] + q[c][7]));
+        sc = wave_sum_d(sc);
+        if ((threadIdx.x & 63) == 0) red[c][wv] = sc;
     }
     __syncthreads();
+#pragma unroll
+    for (int c = 0; c < K; ++c) tot[c] = (red[c][0] + red[c][1]) + (red[c][2] + red[c][3]);
+}
+
+// Sum of the nb block sums (fixed order) and the scalar update of each step;
+// RD_T also sums the ns block sums of |s|^2.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_reduce(SolveArgs a, int nb, int ns) {
+    SolveState* st = a.st;
+    if (MODE != RD_R0 && MODE != RD_TRUE && st->status != RUNNING) return;
+    double tot[2], ss[1] = {0.0};
+    sum_parts<2>(a.part, nb, tot);
+    if (MODE == RD_T) {
+        __syncthreads();
+        sum_parts<1>(a.part_s, ns, ss);
+    }
     if (threadIdx.x != 0) return;
-    const double tot[2] = {(red[0][0] + red[0][1]) + (red[0][2] + red[0][3]),
-                           (red[1][0] + red[1][1]) + (red[1][2] + red[1][3])};
     if (MODE == RD_R0) {
         st->rr = tot[0];
         st->rr0 = tot[0];
@@ -363,10 +383,11 @@ __global__ __launch_bounds__(256) void k_reduce(SolveArgs a, int nb) {
             st->status = RBF_SOLVE_BREAKDOWN;
         else
             st->alpha = st->rho / tot[0];
-    } else if (MODE == RD_S) {
-        if (tot[0] <= st->tol2) st->half = 1;
     } else if (MODE == RD_T) {
-        if (!(tot[1] > 0.0) || !isfinite(tot[0]) || !isfinite(tot[1]))
+        if (ss[0] <= st->tol2) {  // converged at the half step: x += alpha p
+            st->half = 1;
+            st->omega = 0.0;
+        } else if (!(tot[1] > 0.0) || !isfinite(tot[0]) || !isfinite(tot[1]))
             st->status = RBF_SOLVE_BREAKDOWN;
         else
             st->omega = tot[0] / tot[1];
@@ -397,9 +418,14 @@ constexpr int BJ = 64;   // nodes per block (one per lane)
 constexpr int BJ_PER_CELL_2D = 8, BJ_PER_CELL_3D = 16;
 
 struct BjLayout {
-    size_t perm, inv, binv, scratch, total;
+    size_t perm, inv, binv, bscale, scratch, total;
     int64_t nblocks;
 };
+
+// float16 entries of an inverse row scaled by its largest magnitude; element
+// (k, j) of block b at binv[b][j / 8][k][j % 8], the scale of row k at
+// bscale[b][k]
+typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 
 BjLayout bj_layout(int64_t N, int d) {
     BjLayout L;
@@ -410,7 +436,9 @@ BjLayout bj_layout(int64_t N, int d) {
     L.inv = o;
     o += rbf_align(sizeof(int32_t) * N);
     L.binv = o;
-    o += rbf_align(sizeof(float) * BJ * BJ * L.nblocks);
+    o += rbf_align(sizeof(_Float16) * BJ * BJ * L.nblocks);
+    L.bscale = o;
+    o += rbf_align(sizeof(float) * BJ * L.nblocks);
     L.scratch = o;
     o += rbf_align(rbf::cell_order_ws(N, d));
     L.total = o;
@@ -427,20 +455,23 @@ __global__ __launch_bounds__(256) void k_bj_inverse_perm(const int32_t* __restri
 // row l of [A | I] (A gathered from the row of node perm[64 b + l] through LDS,
 // entries outside the block dropped, duplicates added), float32 Gauss-Jordan
 // with partial pivoting (the pivot row by lane reads), then row k of the
-// inverse, (I part) / U_kk of the row pivoted at step k, is stored in the
-// layout of the product: element (k, j) at [j / 4][k][j % 4] of the block.  A
-// block with a zero or non-finite pivot stores the inverse of its diagonal
-// (Jacobi; identity where that is zero).  Padding rows past N are identity.
+// inverse, (I part) / U_kk of the row pivoted at step k, is divided by its
+// largest magnitude and stored as float16 in the layout of the product, the
+// scale beside it.  A block with a zero or non-finite pivot stores the inverse
+// of its diagonal (Jacobi; identity where that is zero).  Padding rows past N
+// are identity.
 __global__ __launch_bounds__(256) void k_bj_setup(int64_t N, const int64_t* __restrict__ offsets,
                                                   const int32_t* __restrict__ idx, const double* __restrict__ vals,
                                                   int64_t nnz, const int32_t* __restrict__ perm,
-                                                  const int32_t* __restrict__ inv, float* __restrict__ binv) {
+                                                  const int32_t* __restrict__ inv, _Float16* __restrict__ binv,
+                                                  float* __restrict__ bscale) {
     __shared__ float As[4][BJ][BJ + 1];
     const int lane = lane_id(), wv = threadIdx.x >> 6;
     const int64_t b = (int64_t)blockIdx.x * 4 + wv;
     if (b * BJ >= N) return;
     const int64_t p = b * BJ + lane;
-    const int node = p < N ? perm[p] : -1;
+    const int32_t pn = p < N ? perm[p] : -1;
+    const int node = (pn >= 0 && (int64_t)pn < N) ? pn : -1;
     float(&Ar)[BJ + 1] = As[wv][lane];
     for (int j = 0; j < BJ; ++j) Ar[j] = 0.0f;
     if (node < 0) {
@@ -487,49 +518,79 @@ __global__ __launch_bounds__(256) void k_bj_setup(int64_t N, const int64_t* __re
         for (int j = 0; j < BJ; ++j) ii[j] = fmaf(-l, readlane_f(ii[j], pl), ii[j]);
     }
     const bool ok = pmin > 0 && pmax < 0x7F800000;  // wave-uniform
-    float* B = binv + (size_t)b * BJ * BJ;
+    _Float16* B = binv + (size_t)b * BJ * BJ;
     if (ok) {
+        float m = 0.0f;
 #pragma unroll
-        for (int j4 = 0; j4 < BJ / 4; ++j4)
-            *reinterpret_cast<float4*>(B + ((size_t)j4 * BJ + mystep) * 4) =
-                make_float4(ii[4 * j4] * invd, ii[4 * j4 + 1] * invd, ii[4 * j4 + 2] * invd, ii[4 * j4 + 3] * invd);
+        for (int j = 0; j < BJ; ++j) m = fmaxf(m, fabsf(ii[j]));
+        const float sc = (m > 0.0f && isfinite(m)) ? m : 1.0f;
+        const float is = 1.0f / sc;
+#pragma unroll
+        for (int j8 = 0; j8 < BJ / 8; ++j8) {
+            half8 h;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) h[q] = (_Float16)(ii[8 * j8 + q] * is);
+            *reinterpret_cast<half8*>(B + ((size_t)j8 * BJ + mystep) * 8) = h;
+        }
+        bscale[b * BJ + mystep] = sc * invd;
     } else {
         const float di = (dg != 0.0f && isfinite(dg)) ? 1.0f / dg : 1.0f;
 #pragma unroll
-        for (int j4 = 0; j4 < BJ / 4; ++j4)
-            *reinterpret_cast<float4*>(B + ((size_t)j4 * BJ + lane) * 4) =
-                make_float4(4 * j4 == lane ? di : 0.0f, 4 * j4 + 1 == lane ? di : 0.0f, 4 * j4 + 2 == lane ? di : 0.0f,
-                            4 * j4 + 3 == lane ? di : 0.0f);
+        for (int j8 = 0; j8 < BJ / 8; ++j8) {
+            half8 h;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) h[q] = (_Float16)(8 * j8 + q == lane ? 1.0f : 0.0f);
+            *reinterpret_cast<half8*>(B + ((size_t)j8 * BJ + lane) * 8) = h;
+        }
+        bscale[b * BJ + lane] = di;
     }
 }
 
-// out = P^-1 in, one wavefront per block (IN_S: the s vector, skipped once the
-// half step has converged).
-template <bool IN_S>
-__global__ __launch_bounds__(256) void k_bj_apply(SolveArgs a) {
+// The p and s updates of the block form (the system in block order, one
+// wavefront per node block), each followed by its block product:
+//   S = false:  p = r + beta (p - omega v),  ph = P^-1 p
+//   S = true:   s = r - alpha v,  sh = P^-1 s,  |s|^2
+// Row k of a block product is scale_k * sum_j h_kj y_j in float64 over the
+// float16 entries h_kj; y_j comes from lane j by lane reads.
+template <bool S>
+__global__ __launch_bounds__(256) void k_bj_vec(SolveArgs a) {
     SolveState* st = a.st;
     if (st->status != RUNNING) return;
-    if (IN_S && st->half) return;
-    const double* in = IN_S ? a.s : a.p;
-    double* out = IN_S ? a.sh : a.ph;
+    const double alpha = st->alpha, omega = st->omega;
+    const double beta = (st->rho / st->rho_prev) * (alpha / omega);
     const int lane = lane_id();
     const int64_t nb = (a.N + BJ - 1) / BJ;
     const int64_t nw = (int64_t)gridDim.x * 4;
+    double c0 = 0.0;
     for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < nb; b += nw) {
-        const int64_t p = b * BJ + lane;
-        const int node = p < a.N ? a.perm[p] : -1;
-        const double y = node >= 0 ? in[node] : 0.0;
-        const float* B = a.binv + (size_t)b * BJ * BJ;
+        const int64_t q = b * BJ + lane;
+        const bool in = q < a.N;
+        double y = 0.0;
+        if (in) {
+            if (S) {
+                y = a.r[q] - alpha * a.v[q];
+                a.s[q] = y;
+                c0 += y * y;
+            } else {
+                y = a.r[q] + beta * (a.p[q] - omega * a.v[q]);
+                a.p[q] = y;
+            }
+        }
+        const half8* B = reinterpret_cast<const half8*>(a.binv + (size_t)b * BJ * BJ) + lane;
+        half8 h[BJ / 8];
+#pragma unroll
+        for (int j8 = 0; j8 < BJ / 8; ++j8) h[j8] = B[(size_t)j8 * BJ];
+        const float sc = a.bscale[b * BJ + lane];
         double acc = 0.0;
 #pragma unroll
-        for (int j4 = 0; j4 < BJ / 4; ++j4) {
-            const float4 m = *reinterpret_cast<const float4*>(B + ((size_t)j4 * BJ + lane) * 4);
-            acc = fma((double)m.x, readlane_d(y, 4 * j4), acc);
-            acc = fma((double)m.y, readlane_d(y, 4 * j4 + 1), acc);
-            acc = fma((double)m.z, readlane_d(y, 4 * j4 + 2), acc);
-            acc = fma((double)m.w, readlane_d(y, 4 * j4 + 3), acc);
-        }
-        if (node >= 0) out[node] = acc;
+        for (int j8 = 0; j8 < BJ / 8; ++j8)
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc = fma((double)(float)h[j8][e], readlane_d(y, 8 * j8 + e), acc);
+        if (in) (S ? a.sh : a.ph)[q] = (double)sc * acc;
+    }
+    if (S) {
+        double tot[1] = {c0};
+        block_partials<1>(tot, a.part_s);
     }
 }
 
@@ -551,29 +612,33 @@ template <int G, int E, int U>
 struct SolverL {
     static hipError_t launch(hipStream_t s, SolveArgs a, int what) {
         const dim3 gr(blocks_for(a.N * G, NBMAX)), gv(blocks_for(a.N, NBVEC)), b(256), one(1);
-        const dim3 gb(blocks_for(((a.N + BJ - 1) / BJ) * 64, 4096));   // one wavefront per node block
-        const int nr = (int)gr.x, nv = (int)gv.x;
+        // one wavefront per node block, at most NBVEC blocks (the |s|^2 block sums)
+        const dim3 gb(blocks_for(((a.N + BJ - 1) / BJ) * 64, NBVEC));
+        const int nr = (int)gr.x, nv = (int)gv.x, ns = a.binv ? (int)gb.x : nv;
         switch (what) {
             case 0:
                 hipLaunchKernelGGL((k_spmv<G, E, U, SP_R0>), gr, b, 0, s, a);
-                hipLaunchKernelGGL((k_reduce<RD_R0>), one, b, 0, s, a, nr);
+                hipLaunchKernelGGL((k_reduce<RD_R0>), one, b, 0, s, a, nr, 0);
                 break;
             case 1:
-                hipLaunchKernelGGL((k_vec<VP>), gv, b, 0, s, a);
-                if (a.perm) hipLaunchKernelGGL((k_bj_apply<false>), gb, b, 0, s, a);
+                if (a.binv)
+                    hipLaunchKernelGGL((k_bj_vec<false>), gb, b, 0, s, a);
+                else
+                    hipLaunchKernelGGL((k_vec<VP>), gv, b, 0, s, a);
                 hipLaunchKernelGGL((k_spmv<G, E, U, SP_V>), gr, b, 0, s, a);
-                hipLaunchKernelGGL((k_reduce<RD_V>), one, b, 0, s, a, nr);
-                hipLaunchKernelGGL((k_vec<VS>), gv, b, 0, s, a);
-                hipLaunchKernelGGL((k_reduce<RD_S>), one, b, 0, s, a, nv);
-                if (a.perm) hipLaunchKernelGGL((k_bj_apply<true>), gb, b, 0, s, a);
+                hipLaunchKernelGGL((k_reduce<RD_V>), one, b, 0, s, a, nr, 0);
+                if (a.binv)
+                    hipLaunchKernelGGL((k_bj_vec<true>), gb, b, 0, s, a);
+                else
+                    hipLaunchKernelGGL((k_vec<VS>), gv, b, 0, s, a);
                 hipLaunchKernelGGL((k_spmv<G, E, U, SP_T>), gr, b, 0, s, a);
-                hipLaunchKernelGGL((k_reduce<RD_T>), one, b, 0, s, a, nr);
+                hipLaunchKernelGGL((k_reduce<RD_T>), one, b, 0, s, a, nr, ns);
                 hipLaunchKernelGGL((k_vec<VX>), gv, b, 0, s, a);
-                hipLaunchKernelGGL((k_reduce<RD_X>), one, b, 0, s, a, nv);
+                hipLaunchKernelGGL((k_reduce<RD_X>), one, b, 0, s, a, nv, 0);
                 break;
             default:
                 hipLaunchKernelGGL((k_spmv<G, E, U, SP_TRUE>), gr, b, 0, s, a);
-                hipLaunchKernelGGL((k_reduce<RD_TRUE>), one, b, 0, s, a, nr);
+                hipLaunchKernelGGL((k_reduce<RD_TRUE>), one, b, 0, s, a, nr, 0);
                 break;
         }
         return hipGetLastError();
@@ -606,9 +671,174 @@ hipError_t solver_launch(int n_max, hipStream_t s, SolveArgs a, int what) {
     return SolverL<64, 4, 1>::launch(s, a, what);
 }
 
-size_t solve_ws_bytes(int64_t N) {
-    return rbf_align(sizeof(SolveState)) + rbf_align((size_t)NBMAX * 2 * sizeof(double)) +
-           9 * rbf_align((size_t)N * sizeof(double));
+// ------------------------------------------------------------------ block order
+// The block-Jacobi solve works on a copy of the system in block order: row q of
+// the copy is row perm[q] of M with every column c replaced by inv[c] (invalid
+// columns stay invalid, -1); a row with an invalid range becomes the single
+// invalid entry -1, so the row products still give NaN for it.  The copy holds
+// nnz + N entries: enough for rows that partition [0, nnz) plus one entry per
+// invalid row; rows of overlapping ranges past that capacity are not copied
+// and fall outside the copy's range check (NaN rows), as invalid rows do.
+constexpr int SCAN_B = 1024;  // elements per block of the offset scan
+
+// len[q] = length of row perm[q] (1 for an invalid range), written to poff[q + 1]
+__global__ __launch_bounds__(256) void k_perm_len(int64_t N, const int64_t* __restrict__ offsets, int64_t nnz,
+                                                  const int32_t* __restrict__ perm, int64_t* __restrict__ poff) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q == 0) poff[0] = 0;
+    if (q >= N) return;
+    const int64_t src = perm[q];
+    if (src < 0 || src >= N) {  // not a permutation of [0, N): the row is invalid
+        poff[q + 1] = 1;
+        return;
+    }
+    const int64_t o = offsets[src], e = offsets[src + 1];
+    poff[q + 1] = (o < 0 || e < o || e > nnz) ? 1 : e - o;
+}
+
+// Inclusive scan of v[0, n) in blocks of SCAN_B: scan within each block, block
+// totals to bsum (k_scan_local); exclusive scan of the totals by one block
+// (k_scan_top); totals of the preceding blocks added (k_scan_add).
+__global__ __launch_bounds__(256) void k_scan_local(int64_t* __restrict__ v, int64_t n, int64_t* __restrict__ bsum) {
+    __shared__ int64_t wsum[4];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_B + threadIdx.x * 4;
+    int64_t e[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) e[k] = base + k < n ? v[base + k] : 0;
+#pragma unroll
+    for (int k = 1; k < 4; ++k) e[k] += e[k - 1];
+    // inclusive scan of the thread totals across the wave, then across the waves
+    int64_t t = e[3];
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t u = __shfl_up(t, o);
+        if (lane >= o) t += u;
+    }
+    if (lane == 63) wsum[wv] = t;
+    __syncthreads();
+    int64_t before = t - e[3];
+    for (int w2 = 0; w2 < wv; ++w2) before += wsum[w2];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (base + k < n) v[base + k] = e[k] + before;
+    if (threadIdx.x == 255) bsum[blockIdx.x] = before + e[3];
+}
+
+__global__ __launch_bounds__(256) void k_scan_top(int64_t* __restrict__ bsum, int64_t nb) {
+    __shared__ int64_t wsum[4];
+    __shared__ int64_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    const int lane = lane_id(), wv = threadIdx.x >> 6;
+    for (int64_t b0 = 0; b0 < nb; b0 += 256) {
+        const int64_t i = b0 + threadIdx.x;
+        const int64_t x = i < nb ? bsum[i] : 0;
+        int64_t t = x;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int64_t u = __shfl_up(t, o);
+            if (lane >= o) t += u;
+        }
+        if (lane == 63) wsum[wv] = t;
+        __syncthreads();
+        int64_t before = carry + t - x;
+        for (int w2 = 0; w2 < wv; ++w2) before += wsum[w2];
+        if (i < nb) bsum[i] = before;  // exclusive
+        __syncthreads();
+        if (threadIdx.x == 255) carry = before + x;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scan_add(int64_t* __restrict__ v, int64_t n,
+                                                  const int64_t* __restrict__ bsum) {
+    const int64_t add = bsum[blockIdx.x];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_B;
+    for (int k = threadIdx.x; k < SCAN_B; k += 256)
+        if (base + k < n) v[base + k] += add;
+}
+
+// row q of the copy (eight lanes per row)
+__global__ __launch_bounds__(256) void k_perm_rows(int64_t N, const int64_t* __restrict__ offsets,
+                                                   const int32_t* __restrict__ idx, const double* __restrict__ vals,
+                                                   int64_t nnz, const int32_t* __restrict__ perm,
+                                                   const int32_t* __restrict__ inv, const int64_t* __restrict__ poff,
+                                                   int32_t* __restrict__ pidx, double* __restrict__ pvals,
+                                                   int64_t cap) {
+    const int gl = threadIdx.x & 7;
+    const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 3;
+    if (q >= N) return;
+    const int64_t src = perm[q];
+    const int64_t dst = poff[q];
+    if (poff[q + 1] > cap) return;
+    const bool sok = src >= 0 && src < N;
+    const int64_t o = sok ? offsets[src] : -1, e = sok ? offsets[src + 1] : -1;
+    if (o < 0 || e < o || e > nnz) {
+        if (gl == 0) {
+            pidx[dst] = -1;
+            pvals[dst] = 0.0;
+        }
+        return;
+    }
+    for (int64_t k = gl; k < e - o; k += 8) {
+        const int32_t c = idx[o + k];
+        pidx[dst + k] = (c >= 0 && (int64_t)c < N) ? inv[c] : -1;
+        pvals[dst + k] = vals[o + k];
+    }
+}
+
+// TO: out[q] = in[perm[q]] for the two vectors; else out[perm[q]] = in[q]
+template <bool TO>
+__global__ __launch_bounds__(256) void k_perm_vec(int64_t N, const int32_t* __restrict__ perm,
+                                                  const double* __restrict__ in0, double* __restrict__ out0,
+                                                  const double* __restrict__ in1, double* __restrict__ out1) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= N) return;
+    const int64_t j = perm[q];
+    const bool ok = j >= 0 && j < N;
+    if (TO) {
+        out0[q] = ok ? in0[j] : kNaN;
+        if (in1) out1[q] = ok ? in1[j] : 0.0;
+    } else if (ok) {
+        out0[j] = in0[q];
+    }
+}
+
+struct SolveLayout {
+    size_t st, part, part_s, vec[9], poff, pidx, pvals, pb, px, bsum, total;
+};
+
+SolveLayout solve_layout(int64_t N, int64_t nnz, bool bj) {
+    SolveLayout L;
+    size_t o = 0;
+    L.st = o;
+    o += rbf_align(sizeof(SolveState));
+    L.part = o;
+    o += rbf_align((size_t)NBMAX * 2 * sizeof(double));
+    L.part_s = o;
+    o += rbf_align((size_t)NBVEC * sizeof(double));
+    for (size_t& v : L.vec) {
+        v = o;
+        o += rbf_align((size_t)N * sizeof(double));
+    }
+    L.poff = L.pidx = L.pvals = L.pb = L.px = L.bsum = 0;
+    if (bj) {
+        L.poff = o;
+        o += rbf_align((size_t)(N + 1) * sizeof(int64_t));
+        L.pidx = o;
+        o += rbf_align((size_t)(nnz + N) * sizeof(int32_t));
+        L.pvals = o;
+        o += rbf_align((size_t)(nnz + N) * sizeof(double));
+        L.pb = o;
+        o += rbf_align((size_t)N * sizeof(double));
+        L.px = o;
+        o += rbf_align((size_t)N * sizeof(double));
+        L.bsum = o;
+        o += rbf_align((size_t)((N + SCAN_B - 1) / SCAN_B) * sizeof(int64_t));
+    }
+    L.total = o;
+    return L;
 }
 
 }  // namespace
@@ -654,18 +884,21 @@ extern "C" rbf_status rbf_block_jacobi_setup(rbf_ctx* ctx, const double* X, int6
     char* w = (char*)pc;
     int32_t* perm = (int32_t*)(w + L.perm);
     int32_t* inv = (int32_t*)(w + L.inv);
-    float* binv = (float*)(w + L.binv);
+    _Float16* binv = (_Float16*)(w + L.binv);
+    float* bscale = (float*)(w + L.bscale);
     RBF_HIP_CHECK(rbf::cell_order_enqueue(s, X, N, d, d == 3 ? BJ_PER_CELL_3D : BJ_PER_CELL_2D, w + L.scratch, perm));
     hipLaunchKernelGGL(k_bj_inverse_perm, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, perm, N, inv);
     hipLaunchKernelGGL(k_bj_setup, dim3((unsigned)((L.nblocks + 3) / 4)), dim3(256), 0, s, N, offsets, idx, vals, nnz,
-                       perm, inv, binv);
+                       perm, inv, binv, bscale);
     RBF_LAUNCH_CHECK();
     return RBF_OK;
 }
 
-extern "C" rbf_status rbf_bicgstab_workspace(int64_t N, size_t* bytes) {
-    if (!bytes || N < 1) return RBF_EINVAL;
-    *bytes = solve_ws_bytes(N);
+extern "C" rbf_status rbf_bicgstab_workspace(int64_t N, int64_t nnz, int precond, size_t* bytes) {
+    if (!bytes || N < 1 || nnz < 0) return RBF_EINVAL;
+    if (precond != RBF_PRECOND_NONE && precond != RBF_PRECOND_JACOBI && precond != RBF_PRECOND_BLOCK_JACOBI)
+        return RBF_EINVAL;
+    *bytes = solve_layout(N, nnz, precond == RBF_PRECOND_BLOCK_JACOBI).total;
     return RBF_OK;
 }
 
@@ -683,7 +916,9 @@ extern "C" rbf_status rbf_bicgstab(rbf_ctx* ctx, int64_t N, const int64_t* offse
     // the block-Jacobi data's size depends on d only through its scratch; the 3D
     // layout is the larger one, the 2D one is the minimum accepted
     if (precond == RBF_PRECOND_BLOCK_JACOBI && pc_bytes < bj_layout(N, 2).total) return RBF_EWORKSPACE;
-    if (ws_bytes < solve_ws_bytes(N)) return RBF_EWORKSPACE;
+    const bool bj = precond == RBF_PRECOND_BLOCK_JACOBI;
+    const SolveLayout WL = solve_layout(N, nnz, bj);
+    if (ws_bytes < WL.total) return RBF_EWORKSPACE;
     if (ranges_overlap(x, (size_t)N * sizeof(double), rhs, (size_t)N * sizeof(double))) return RBF_EINVAL;
     RBF_HIP_CHECK(hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
@@ -697,23 +932,44 @@ extern "C" rbf_status rbf_bicgstab(rbf_ctx* ctx, int64_t N, const int64_t* offse
     a.nnz = nnz;
     a.b = rhs;
     a.x = x;
-    a.st = (SolveState*)w;
-    w += rbf_align(sizeof(SolveState));
-    a.part = (double*)w;
-    w += rbf_align((size_t)NBMAX * 2 * sizeof(double));
+    a.st = (SolveState*)(w + WL.st);
+    a.part = (double*)(w + WL.part);
+    a.part_s = (double*)(w + WL.part_s);
     double** vecs[9] = {&a.dinv, &a.r, &a.rh, &a.p, &a.v, &a.s, &a.t, &a.ph, &a.sh};
-    for (double** q : vecs) {
-        *q = (double*)w;
-        w += rbf_align((size_t)N * sizeof(double));
-    }
-    const bool bj = precond == RBF_PRECOND_BLOCK_JACOBI;
+    for (int k = 0; k < 9; ++k) *vecs[k] = (double*)(w + WL.vec[k]);
+    const int32_t* perm = nullptr;
     if (bj) {
         const BjLayout L = bj_layout(N, 2);  // perm and inverses sit at the same offsets for d = 2 and 3
-        a.perm = (const int32_t*)((const char*)pc + L.perm);
-        a.binv = (const float*)((const char*)pc + L.binv);
+        perm = (const int32_t*)((const char*)pc + L.perm);
+        const int32_t* inv = (const int32_t*)((const char*)pc + L.inv);
+        a.binv = (const _Float16*)((const char*)pc + L.binv);
+        a.bscale = (const float*)((const char*)pc + L.bscale);
+        // the system in block order
+        int64_t* poff = (int64_t*)(w + WL.poff);
+        int32_t* pidx = (int32_t*)(w + WL.pidx);
+        double* pvals = (double*)(w + WL.pvals);
+        int64_t* bsum = (int64_t*)(w + WL.bsum);
+        const int64_t nsb = (N + SCAN_B - 1) / SCAN_B;
+        const unsigned gN = (unsigned)((N + 255) / 256);
+        hipLaunchKernelGGL(k_perm_len, dim3(gN), dim3(256), 0, s, N, offsets, nnz, perm, poff);
+        hipLaunchKernelGGL(k_scan_local, dim3((unsigned)nsb), dim3(256), 0, s, poff + 1, N, bsum);
+        hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(256), 0, s, bsum, nsb);
+        hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nsb), dim3(256), 0, s, poff + 1, N, bsum);
+        hipLaunchKernelGGL(k_perm_rows, dim3((unsigned)((N * 8 + 255) / 256)), dim3(256), 0, s, N, offsets, idx, vals,
+                           nnz, perm, inv, poff, pidx, pvals, nnz + N);
+        double* pb = (double*)(w + WL.pb);
+        double* px = (double*)(w + WL.px);
+        hipLaunchKernelGGL((k_perm_vec<true>), dim3(gN), dim3(256), 0, s, N, perm, rhs, pb, (const double*)x, px);
+        RBF_LAUNCH_CHECK();
+        a.offsets = poff;
+        a.idx = pidx;
+        a.vals = pvals;
+        a.nnz = nnz + N;
+        a.b = pb;
+        a.x = px;
     } else {
-        a.perm = nullptr;
         a.binv = nullptr;
+        a.bscale = nullptr;
     }
     a.xp = bj ? a.ph : a.p;
     a.xs = bj ? a.sh : a.s;
@@ -736,6 +992,9 @@ extern "C" rbf_status rbf_bicgstab(rbf_ctx* ctx, int64_t N, const int64_t* offse
         enqueued += chunk;
     }
     if (solver_launch(n_max, s, a, 2) != hipSuccess) return RBF_EHIP;
+    if (bj)
+        hipLaunchKernelGGL((k_perm_vec<false>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, perm,
+                           (const double*)a.x, x, (const double*)nullptr, (double*)nullptr);
     RBF_HIP_CHECK(hipMemcpyAsync(&hs, a.st, sizeof(hs), hipMemcpyDeviceToHost, s));
     RBF_HIP_CHECK(hipStreamSynchronize(s));
     if (info) {

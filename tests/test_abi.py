@@ -163,15 +163,21 @@ def test_more_host_argument_errors_without_gpu(lib_path):
                                ctypes.c_double(0.1), None) == -1
     assert L.rbf_assemble_implicit(None, one, 2, None, None, one, None, None, None, None, None, None, None,
                                    None) == -1
-    assert L.rbf_bicgstab_workspace(ctypes.c_int64(0), ctypes.byref(b)) == -1
-    assert L.rbf_bicgstab_workspace(ctypes.c_int64(1000), None) == -1
-    assert L.rbf_bicgstab_workspace(ctypes.c_int64(1000), ctypes.byref(b)) == 0
-    assert b.value >= 9 * 1000 * 8 + 4096 * 8
+    I64 = ctypes.c_int64
+    assert L.rbf_bicgstab_workspace(I64(0), I64(0), 1, ctypes.byref(b)) == -1
+    assert L.rbf_bicgstab_workspace(I64(1000), I64(9000), 1, None) == -1
+    assert L.rbf_bicgstab_workspace(I64(1000), I64(-1), 1, ctypes.byref(b)) == -1
+    assert L.rbf_bicgstab_workspace(I64(1000), I64(9000), 7, ctypes.byref(b)) == -1
+    assert L.rbf_bicgstab_workspace(I64(1000), I64(9000), 1, ctypes.byref(b)) == 0
+    assert b.value >= 9 * 1000 * 8 + 6144 * 8
+    jac = b.value
+    assert L.rbf_bicgstab_workspace(I64(1000), I64(9000), 2, ctypes.byref(b)) == 0
+    assert b.value >= jac + 12 * (9000 + 1000) + 24 * 1000
     assert L.rbf_bicgstab(None, one, None, None, None, one, 1, None, None, ctypes.c_double(1e-8), 10, 1, None,
                           ctypes.c_size_t(0), None, ctypes.c_size_t(0), None) == -1
     assert L.rbf_block_jacobi_size(ctypes.c_int64(1000), 4, ctypes.byref(b)) == -3
     assert L.rbf_block_jacobi_size(ctypes.c_int64(1000), 3, ctypes.byref(b)) == 0
-    assert b.value >= 1000 * (8 + 256)
+    assert b.value >= 1000 * (8 + 128 + 4)  # node order and its inverse, float16 rows and their scales
 
 
 def test_node_kind_and_solver_constants_match_the_binding():

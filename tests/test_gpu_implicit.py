@@ -191,9 +191,11 @@ def test_3d_neumann_reports_failure(gpu):
         assert info["status"] in (rb.SOLVE_MAXITER, rb.SOLVE_DIVERGED, rb.SOLVE_BREAKDOWN)
 
 
-def test_bicgstab_csr_with_ragged_rows(gpu):
+@pytest.mark.parametrize("precond", ["jacobi", "block_jacobi"])
+def test_bicgstab_csr_with_ragged_rows(gpu, precond):
     """The solver on CSR input: columns ascending (the diagonal anywhere in a row),
-    explicit zeros dropped so that Dirichlet rows hold one entry."""
+    explicit zeros dropped so that Dirichlet rows hold one entry (block-Jacobi:
+    the copy in block order has rows of every length)."""
     rb = _rb()
     nd, kind, normals, off, idx, W, f, g, u0 = _annulus_problem(0.025, neumann=False)
     vals, rhs = implicit.assemble(off, idx, W[0], W[1:], kind, normals, f=f, g=g)
@@ -204,42 +206,60 @@ def test_bicgstab_csr_with_ragged_rows(gpu):
     assert lens.min() == 1 and lens.max() == 30
     ud = implicit.solve(off, idx, vals, rhs)
     tol = 1e-12
-    x, info = rb.bicgstab(_t(M.indptr.astype(np.int64), gpu), _t(M.indices.astype(np.int32), gpu), _t(M.data, gpu),
-                          30, _t(rhs, gpu), tol=tol, max_iter=20000, precond="jacobi")
+    T = [_t(M.indptr.astype(np.int64), gpu), _t(M.indices.astype(np.int32), gpu), _t(M.data, gpu)]
+    pc = rb.block_jacobi(_t(nd.X, gpu), *T) if precond == "block_jacobi" else None
+    x, info = rb.bicgstab(*T, 30, _t(rhs, gpu), tol=tol, max_iter=20000, precond=precond, pc=pc)
     assert info["status"] == rb.SOLVE_CONVERGED, info
     xh = x.cpu().numpy()
-    dinv = 1.0 / M.diagonal()
+    dinv = 1.0 / M.diagonal() if precond == "jacobi" else np.ones(nd.N)
     assert np.linalg.norm(dinv * (rhs - M @ xh)) / np.linalg.norm(dinv * rhs) <= 10 * tol
     assert np.abs(xh - ud).max() <= 1e5 * 10 * tol * np.abs(ud).max()
 
 
-def test_bicgstab_outcomes(gpu):
+@pytest.mark.parametrize("precond", ["jacobi", "block_jacobi"])
+def test_bicgstab_outcomes(gpu, precond):
     rb = _rb()
     nd, kind, normals, off, idx, W, f, g, _ = _annulus_problem(0.05)
     vals, rhs = implicit.assemble(off, idx, W[0], W[1:], kind, normals, f=f, g=g)
     n_max = int(np.diff(off).max())
     to = lambda a: _t(a, gpu)  # noqa: E731
+    pc = rb.block_jacobi(to(nd.X), to(off), to(idx), to(vals)) if precond == "block_jacobi" else None
+    kw = dict(precond=precond, pc=pc)
     # iteration limit
-    x, info = rb.bicgstab(to(off), to(idx), to(vals), n_max, to(rhs), tol=1e-14, max_iter=3)
+    x, info = rb.bicgstab(to(off), to(idx), to(vals), n_max, to(rhs), tol=1e-14, max_iter=3, **kw)
     assert info["status"] == rb.SOLVE_MAXITER and info["iterations"] == 3
-    # the exact solution as the initial guess: converged without iterating
+    # the exact solution as the initial guess: converged without iterating, x
+    # returned bit for bit (block-Jacobi: through the copy in block order and back)
     ud = implicit.solve(off, idx, vals, rhs)
-    x, info = rb.bicgstab(to(off), to(idx), to(vals), n_max, to(rhs), x=to(ud), tol=1e-6)
+    x, info = rb.bicgstab(to(off), to(idx), to(vals), n_max, to(rhs), x=to(ud), tol=1e-6, **kw)
     assert info["status"] == rb.SOLVE_CONVERGED and info["iterations"] == 0
     assert np.array_equal(x.cpu().numpy(), ud)
     # zero right-hand side from zero: converged at once, x stays zero
-    x, info = rb.bicgstab(to(off), to(idx), to(vals), n_max, torch.zeros(nd.N, dtype=torch.float64, device=gpu))
+    x, info = rb.bicgstab(to(off), to(idx), to(vals), n_max, torch.zeros(nd.N, dtype=torch.float64, device=gpu),
+                          **kw)
     assert info["status"] == rb.SOLVE_CONVERGED and info["iterations"] == 0 and torch.count_nonzero(x).item() == 0
-    # a zero diagonal entry with Jacobi scaling
-    v2 = vals.copy()
-    i = np.where(kind == hc.INTERIOR)[0][3]
-    v2[off[i]] = 0.0
-    x, info = rb.bicgstab(to(off), to(idx), to(v2), n_max, to(rhs), precond="jacobi")
-    assert info["status"] == rb.SOLVE_BADDIAG
+    if precond == "jacobi":
+        # a zero diagonal entry with Jacobi scaling
+        v2 = vals.copy()
+        i = np.where(kind == hc.INTERIOR)[0][3]
+        v2[off[i]] = 0.0
+        x, info = rb.bicgstab(to(off), to(idx), to(v2), n_max, to(rhs), **kw)
+        assert info["status"] == rb.SOLVE_BADDIAG
     # non-finite input: breakdown, never a hang
     r2 = rhs.copy()
     r2[5] = np.nan
-    x, info = rb.bicgstab(to(off), to(idx), to(vals), n_max, to(r2))
+    x, info = rb.bicgstab(to(off), to(idx), to(vals), n_max, to(r2), **kw)
+    assert info["status"] == rb.SOLVE_BREAKDOWN
+    # a row with an invalid range (end before start) or an index outside [0, N)
+    # gives a NaN row product: breakdown
+    # (Jacobi: the row has no diagonal entry either)
+    o2 = off.copy()
+    o2[7] = o2[8] + 1
+    x, info = rb.bicgstab(to(o2), to(idx), to(vals), n_max, to(rhs), **kw)
+    assert info["status"] == (rb.SOLVE_BADDIAG if precond == "jacobi" else rb.SOLVE_BREAKDOWN)
+    i2 = idx.copy()
+    i2[off[11] + 2] = nd.N + 5
+    x, info = rb.bicgstab(to(off), to(i2), to(vals), n_max, to(rhs), **kw)
     assert info["status"] == rb.SOLVE_BREAKDOWN
     with pytest.raises(rb.RbfError):
         rb.bicgstab(to(off), to(idx), to(vals), n_max, to(rhs), precond="ilu")
