@@ -65,12 +65,12 @@ ORD = {"lap": 2, "dx": 1, "dy": 1, "dz": 1}
 CSRC = "paper_1912_13282_amd/csrc/"
 TRAFFIC = {
     "cube_sphere3d": ("profiles/traffic_weights_cube_minus_sphere_3d.txt",
-                      [CSRC + f for f in ("common.hpp", "wsolve.hpp", "weights_kernels.hpp", "weights.hip",
-                                          "wcls_56.hip")]),
+                      [CSRC + f for f in ("common.hpp", "wsolve.hpp", "wsolve_pair.hpp", "weights_kernels.hpp",
+                                          "weights.hip", "wcls_56.hip")]),
     "explicit": ("profiles/traffic_apply_explicit_heat_cube_minus_sphere_3d.txt",
                  [CSRC + f for f in ("common.hpp", "rowdot.hpp", "apply.hip")]),
-    "poisson3d": ("profiles/traffic_spmv_poisson_annulus_3d.txt",
-                  [CSRC + f for f in ("common.hpp", "rowdot.hpp", "implicit.hip")]),
+    "poisson3d": ("profiles/traffic_bicgstab_block_jacobi_poisson_annulus_3d.txt",
+                  [CSRC + f for f in ("common.hpp", "rowdot.hpp", "cellorder.hpp", "implicit.hip")]),
 }
 
 
@@ -551,8 +551,9 @@ def bench_mixed(a, torch, rb, B):
                      "step": "select_stencils x4 + compute_weights_batched + assemble_csr x4"})
     out["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                        "frac": achieved / PEAK_FP64_TFLOPS, "traffic": None,
-                       "kernel": "k_bpersist (refined pass + FP64 fallback pass)" if a.form == "f32_ir"
-                       else "k_bpersist", "flop_per_stencil": flop_total / N_total, "stencils_per_launch": N_total}
+                       "kernel": "k_bclass, k_bclass_pair, k_bclass_quad: one persistent launch per size class "
+                                 "(refined pass + FP64 fallback pass)" if a.form == "f32_ir"
+                       else "k_bclass, k_bclass_quad: one persistent launch per size class", "flop_per_stencil": flop_total / N_total, "stencils_per_launch": N_total}
     out["forms"] = results
     if "f64" in results and "f32_ir" in results:
         out["mixed_vs_f64"] = (results["f32_ir"]["knn_weights_stencils_per_s"] /
@@ -629,6 +630,14 @@ def bench_learned(a, torch, rb, B):
         quality[nm] = {"poisson_max_err": opoi.solve_dirichlet(q.X, q.is_boundary, oq.cpu().numpy(), iqn, wn)[1],
                        "e_h": float(np.abs(approx - opoi.lap_u0(q.X))[~q.is_boundary].max())}
     quality["accepted_fraction"] = float((stq.cpu().numpy() == rb.ST_SURROGATE).mean())
+    # the acceptance gate on the projection's correction, max|w - y| <= corr_tol max|w|: tighter
+    # gates send more stencils to the plain solve and bring the Poisson error towards the plain one
+    quality["gate_sweep"] = []
+    for ct in (0.25, 0.1, 0.05, 0.02):
+        wg, sg = S.surrogate_laplacian(Xq, oq, iq, st.params, corr_tol=ct)
+        quality["gate_sweep"].append({
+            "corr_tol": ct, "accepted_fraction": float((sg.cpu().numpy() == rb.ST_SURROGATE).mean()),
+            "poisson_max_err": opoi.solve_dirichlet(q.X, q.is_boundary, oq.cpu().numpy(), iqn, wg.cpu().numpy())[1]})
 
     # throughput on a 1.7M-node disk
     nd = ns.disk(ns.DISK_H / 30.0, 1001)
@@ -1073,9 +1082,40 @@ def bench_counters(a, torch, rb, B):
         rb.assemble_csr(off, idx, w, n, ctx=ctx)
         torch.cuda.synchronize()
         ran.append(dict(N=nd.N, n=n, degree=P, forms=list(forms)))
+        print(f"[bench] counters: {ran[-1]}", file=sys.stderr, flush=True)
+        return off, idx, w
 
     wl = ns.workload("cube_sphere3d")
-    uniform(wl["nodes"][0], wl["n"], wl["P"], wl["ops"], ("f64", "f32_ir"))
+    nd = wl["nodes"][0]
+    off, idx, w = uniform(nd, wl["n"], wl["P"], wl["ops"], ("f64", "f32_ir"))
+    # the explicit workload's kernels on the same stencils: the four operators
+    # applied to a field, and one explicit step with Dirichlet rows only
+    u = torch.from_numpy(np.sin(nd.X[:, 0]) * nd.X[:, 1]).to(dev)
+    rb.apply_operators(off, idx, w, wl["n"], u, ctx=ctx)
+    kt = torch.from_numpy(np.where(nd.is_boundary, rb.NODE_DIRICHLET, rb.NODE_INTERIOR).astype(np.uint8)).to(dev)
+    rb.explicit_step(off, idx, wl["n"], w[0], kt, u, 0.02 * ns.CUBE_SPHERE_H ** 2, g=u, ctx=ctx)
+    torch.cuda.synchronize()
+    ran.append(dict(explicit_N=nd.N))
+    print(f"[bench] counters: {ran[-1]}", file=sys.stderr, flush=True)
+    del off, idx, w, u, kt
+    # the 3D Poisson system of Sec. 5: twenty BiCGStab iterations with each preconditioner
+    from oracle import poisson as opoi
+    d3, n3, P3, h3 = POISSON_CASES["poisson3d"]
+    nd = ns.annulus(h3, 1006, d=d3)
+    X = torch.from_numpy(nd.X).to(dev)
+    off = torch.from_numpy(ns.offsets_from_sizes(np.full(nd.N, n3, dtype=np.int64))).to(dev)
+    idx = rb.select_stencils(X, off, n3, ctx=ctx)
+    w, _ = rb.compute_weights(X, off, idx, n3, P3, ("lap",), precision="f64", ctx=ctx)
+    kind = torch.from_numpy(np.where(nd.is_boundary, rb.NODE_DIRICHLET, rb.NODE_INTERIOR).astype(np.uint8)).to(dev)
+    vals, rhs = rb.assemble_implicit(off, idx, w[0], kind, f=torch.from_numpy(opoi.lap_u0(nd.X)).to(dev),
+                                     g=torch.from_numpy(opoi.u0(nd.X)).to(dev), d=d3, ctx=ctx)
+    pc = rb.block_jacobi(X, off, idx, vals, ctx=ctx)
+    for pre in ("jacobi", "block_jacobi"):
+        rb.bicgstab(off, idx, vals, n3, rhs, tol=1e-30, max_iter=20, precond=pre, ctx=ctx, pc=pc)
+    torch.cuda.synchronize()
+    ran.append(dict(poisson3d_N=nd.N, iterations=20, preconds=["jacobi", "block_jacobi"]))
+    print(f"[bench] counters: {ran[-1]}", file=sys.stderr, flush=True)
+    del X, off, idx, w, kind, vals, rhs, pc
     wl = ns.workload("large3d", h=1.0 / 100)
     uniform(wl["nodes"][0], wl["n"], wl["P"], wl["ops"], ("f64", "f32_ir"))
     doms = []
@@ -1089,6 +1129,7 @@ def bench_counters(a, torch, rb, B):
         rb.compute_weights_batched(doms, precision=f, ctx=ctx)
     torch.cuda.synchronize()
     ran.append(dict(mixed_stencils=int(sum(D.X.shape[0] for D in doms)), forms=["batched f64", "batched f32_ir"]))
+    print(f"[bench] counters: {ran[-1]}", file=sys.stderr, flush=True)
     del doms
     # the surrogate: a seeded network (its operation counts do not depend on the values)
     nd = ns.disk(ns.DISK_H / 30.0, 1001)

@@ -166,9 +166,11 @@ rbf_status rbf_select_stencils_static(rbf_ctx* ctx, const double* X, int64_t N, 
  * degree lies outside [0, degree_max] gets RBF_ST_BADSIZE; with degree == NULL
  * every node takes degree_max.  n_max bounds every n_i; the system size
  * n_max + C(degree_max + d, d) must be <= 128, and selects the compiled size
- * class every stencil of the call runs in.  Systems above 64 unknowns are
- * solved in float64 (LU, two rows per lane) also when F32_IR is asked for, and
- * then report RBF_ST_FALLBACK.  status[N] (int8, may be NULL for F64) receives
+ * class every stencil of the call runs in.  F32_IR runs the float32
+ * elimination with one row per lane up to 64 unknowns and two rows per lane
+ * (one wavefront per stencil) up to 108; the 128 class is solved in float64
+ * (four wavefronts per stencil) also when F32_IR is asked for, and then reports
+ * RBF_ST_FALLBACK.  status[N] (int8, may be NULL for F64) receives
  * RBF_ST_*.  w: [popcount(op_mask)][nnz] float64, popcount(op_mask) <= 4.
  * No workspace is needed.
  * ------------------------------------------------------------------------ */

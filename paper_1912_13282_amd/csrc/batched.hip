@@ -34,23 +34,44 @@ __global__ __launch_bounds__(64) void k_bzero(int* __restrict__ counts) {
     if (threadIdx.x <= BREJECT) counts[threadIdx.x] = 0;
 }
 
+// The ranks come from one atomic per class present in a wavefront (the lanes of
+// a class take consecutive ranks after the wave's base), not one per stencil:
+// with a handful of classes, per-stencil atomics on the same few counters
+// serialise.
 __global__ __launch_bounds__(256) void k_bclassify(const BParams* __restrict__ bpp, int* __restrict__ counts,
                                                    uint32_t* __restrict__ cls_rank) {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const BParams& bp = *bpp;
-    if (g >= bp.total) return;
-    const BDom& D = bp.dom[find_dom(bp, g)];
-    const int64_t i = g - D.first;
-    const int P = D.degree ? (int)D.degree[i] : D.a.P;
-    const int64_t off = D.a.offsets[i];
-    const int64_t n = D.a.offsets[i + 1] - off;
+    const bool in = g < bp.total;
     int c = BREJECT;
-    if (P >= 0 && P <= 4 && n >= 1 && n <= D.a.n_max && off >= 0 && off + n <= D.a.nnz) {
-        const int M = (int)n + binom(P + D.a.d, D.a.d);
-        for (int k = NBCLS - 1; k >= 0; --k)
-            if (M <= bcls_maxm(k)) c = k;
+    if (in) {
+        const BDom& D = bp.dom[find_dom(bp, g)];
+        const int64_t i = g - D.first;
+        const int P = D.degree ? (int)D.degree[i] : D.a.P;
+        const int64_t off = D.a.offsets[i];
+        const int64_t n = D.a.offsets[i + 1] - off;
+        if (P >= 0 && P <= 4 && n >= 1 && n <= D.a.n_max && off >= 0 && off + n <= D.a.nnz) {
+            const int M = (int)n + binom(P + D.a.d, D.a.d);
+            for (int k = NBCLS - 1; k >= 0; --k)
+                if (M <= bcls_maxm(k)) c = k;
+        }
     }
-    const int r = atomicAdd(&counts[c], 1);
+    const int lane = lane_id();
+    uint64_t rem = ballot64(in);
+    int r = 0;
+    while (rem) {  // wave-uniform: one pass per class present
+        const int leader = first_lane(rem);
+        const int cl = __builtin_amdgcn_readlane(c, leader);
+        const uint64_t same = ballot64(in && c == cl);
+        int base = 0;
+        if (lane == leader) base = atomicAdd(&counts[cl], __builtin_popcountll(same));
+        base = __builtin_amdgcn_readlane(base, leader);
+        if (in && c == cl)
+            r = base + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(same >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo((unsigned)same, 0u));
+        rem &= ~same;
+    }
+    if (!in) return;
     cls_rank[2 * g] = (uint32_t)c;
     cls_rank[2 * g + 1] = (uint32_t)r;
 }

@@ -317,37 +317,40 @@ __global__ __launch_bounds__(256) void k_vec(SolveArgs a) {
 
 enum { RD_R0, RD_V, RD_T, RD_X, RD_TRUE };
 
-// Sum of the nb block sums part[b][K] in a fixed order, by the whole block;
-// the totals are valid in thread 0.
-template <int K>
-__device__ __forceinline__ void sum_parts(const double* part, int nb, double (&tot)[K]) {
-    __shared__ double red[K][4];
-    // eight independent accumulators per thread keep eight loads in flight;
-    // they are combined in a fixed order
-    double q[K][8];
+// Sums of the nb block sums part[b][0..1] and (S) the ns block sums ps[b], each
+// in a fixed order, by the whole block; the totals are valid in thread 0.
+template <bool S>
+__device__ __forceinline__ void sum_parts(const double* part, int nb, const double* ps, int ns, double (&tot)[3]) {
+    __shared__ double red[3][4];
+    // eight independent accumulators per thread and sum keep the loads of both
+    // arrays in flight together; they are combined in a fixed order
+    double q[3][8];
 #pragma unroll
-    for (int c = 0; c < K; ++c)
+    for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int k = 0; k < 8; ++k) q[c][k] = 0.0;
-    for (int b0 = threadIdx.x; b0 < nb; b0 += 8 * 256) {
+    const int nm = S && ns > nb ? ns : nb;
+    for (int b0 = threadIdx.x; b0 < nm; b0 += 8 * 256) {
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int b = b0 + k * 256;
-            if (b < nb)
-#pragma unroll
-                for (int c = 0; c < K; ++c) q[c][k] += part[K * b + c];
+            if (b < nb) {
+                q[0][k] += part[2 * b];
+                q[1][k] += part[2 * b + 1];
+            }
+            if (S && b < ns) q[2][k] += ps[b];
         }
     }
     const int wv = threadIdx.x >> 6;
 #pragma unroll
-    for (int c = 0; c < K; ++c) {
+    for (int c = 0; c < (S ? 3 : 2); ++c) {
         double sc = ((q[c][0] + q[c][1]) + (q[c][2] + q[c][3])) + ((q[c][4] + q[c][5]) + (q[c][6] + q[c][7]));
         sc = wave_sum_d(sc);
         if ((threadIdx.x & 63) == 0) red[c][wv] = sc;
     }
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < K; ++c) tot[c] = (red[c][0] + red[c][1]) + (red[c][2] + red[c][3]);
+    for (int c = 0; c < 3; ++c) tot[c] = (S || c < 2) ? (red[c][0] + red[c][1]) + (red[c][2] + red[c][3]) : 0.0;
 }
 
 // Sum of the nb block sums (fixed order) and the scalar update of each step;
@@ -356,12 +359,9 @@ template <int MODE>
 __global__ __launch_bounds__(256) void k_reduce(SolveArgs a, int nb, int ns) {
     SolveState* st = a.st;
     if (MODE != RD_R0 && MODE != RD_TRUE && st->status != RUNNING) return;
-    double tot[2], ss[1] = {0.0};
-    sum_parts<2>(a.part, nb, tot);
-    if (MODE == RD_T) {
-        __syncthreads();
-        sum_parts<1>(a.part_s, ns, ss);
-    }
+    double tot[3];
+    sum_parts<MODE == RD_T>(a.part, nb, a.part_s, ns, tot);
+    const double ss[1] = {tot[2]};
     if (threadIdx.x != 0) return;
     if (MODE == RD_R0) {
         st->rr = tot[0];
