@@ -556,6 +556,8 @@ __global__ __launch_bounds__(256) void k_knn_list(const GridParams* __restrict__
 constexpr int RCAP = 128;
 constexpr int RTRIES = 6;
 constexpr int RADIUS_KMAX = 100;  // survivors aimed at 1.25 k must fit RCAP
+constexpr int RANK_MAX = 32;      // survivors ordered by counting ranks up to this many
+static_assert(RANK_MAX % 2 == 0 && RANK_MAX < RCAP, "the rank loop reads slot count when count is odd");
 
 // Nodes in the cell rows of `rows` (rows of cells along x, y/z from the row
 // index) within radius rho of qx: lane r handles row r0 + r, returns its node
@@ -585,8 +587,8 @@ __global__ __launch_bounds__(256) void k_knn_radius(const GridParams* __restrict
                                                     int64_t N, int d, const int64_t* __restrict__ offsets, int n_max,
                                                     int32_t* __restrict__ idx, double key_inf,
                                                     int* __restrict__ list, int* __restrict__ list_count) {
-    __shared__ double skey[4][RCAP];
-    __shared__ unsigned sid[4][RCAP];
+    __shared__ __attribute__((aligned(16))) double skey[4][RCAP];
+    __shared__ __attribute__((aligned(16))) unsigned sid[4][RCAP];
     const GridParams g = *gpp;
     const int lane = lane_id(), wv = threadIdx.x / WAVE;
     const int64_t q = (int64_t)blockIdx.x * 4 + wv;
@@ -702,7 +704,26 @@ __global__ __launch_bounds__(256) void k_knn_radius(const GridParams* __restrict
         return;
     }
     wave_lds_sync();
-    if (count <= WAVE) {
+    if (count <= RANK_MAX) {
+        // few survivors: each lane's survivor counts the survivors before it on
+        // (key, index) -- a strict order, so the ranks are 0 .. count - 1 -- and
+        // the k smallest ranks are the stencil in order (fewer instructions than
+        // the 21 stages of a 64-wide sort)
+        const bool have = lane < count;
+        const double kl = have ? skey[wv][lane] : 0.0;
+        const unsigned il = have ? sid[wv][lane] : 0u;
+        int rank = 0;
+        // two survivors per 16-byte read (slot count, read when count is odd, is
+        // within the buffer and not counted)
+#pragma unroll 4
+        for (int j = 0; j < count; j += 2) {
+            const double2 kk = *reinterpret_cast<const double2*>(&skey[wv][j]);
+            const uint2 ii = *reinterpret_cast<const uint2*>(&sid[wv][j]);
+            rank += (kk.x < kl || (kk.x == kl && ii.x < il)) ? 1 : 0;
+            rank += (j + 1 < count && (kk.y < kl || (kk.y == kl && ii.y < il))) ? 1 : 0;
+        }
+        if (have && rank < k) idx[off + 1 + rank] = (int32_t)il;
+    } else if (count <= WAVE) {
         double K[1];
         unsigned I[1];
         K[0] = lane < count ? skey[wv][lane] : key_inf;
