@@ -1154,11 +1154,13 @@ def leg_summary(o):
 
 
 def legs(a, torch, rb, B):
-    """Compact runs of the other two throughput workloads, reported beside the main
-    line: the 16.3M-node large-3D set (plain FP64 vs FP32+refine vs the batched
-    persistent form, with CSR) and the 8.1M-stencil mixed 2D/3D batch (per-class
-    plans tuned per precision); one warm-up and one timed step per form, weights
-    checked against the oracle on a seeded sample."""
+    """Compact runs of the other three throughput workloads, reported beside the
+    main line: the 16.3M-node large-3D set (plain FP64 vs FP32+refine vs the
+    batched persistent form, with CSR), the 8.1M-stencil mixed 2D/3D batch
+    (per-class plans tuned per precision), one warm-up and one timed step per
+    form, weights checked against the oracle on a seeded sample; and the learned
+    Laplacian (training on the GPU, then the surrogate against FP64 and FP32 +
+    refinement on a 1.7M-node disk, three timed steps)."""
     import copy
     out = {}
     la = copy.copy(a)
@@ -1173,6 +1175,16 @@ def legs(a, torch, rb, B):
     t = time.perf_counter()
     out["mixed"] = leg_summary(bench_mixed(lm, torch, rb, B))
     out["mixed"]["leg_wall_s"] = time.perf_counter() - t
+    torch.cuda.empty_cache()
+    ll = copy.copy(la)
+    ll.steps, ll.warmup = 3, 1
+    t = time.perf_counter()
+    o = bench_learned(ll, torch, rb, B)
+    out["learned"] = {k: o[k] for k in ("value", "unit", "ms_per_step", "dtype", "config", "roofline", "quality",
+                                        "learned_vs_f64") if k in o}
+    out["learned"]["forms"] = {f: {k: v[k] for k in ("ms_per_step", "phases_ms", "stencils_per_s", "status_counts")}
+                               for f, v in o["forms"].items()}
+    out["learned"]["leg_wall_s"] = time.perf_counter() - t
     torch.cuda.empty_cache()
     return out
 

@@ -24,6 +24,8 @@
 
 namespace rbf {
 
+constexpr int QB = 8;  // pivot-row reads in flight per batch of the update
+
 template <int H>
 struct QuadLds {
     static constexpr int M2 = 2 * H;
@@ -93,12 +95,24 @@ __device__ __forceinline__ void quad_eliminate(double (&row)[H], double (&rhs)[N
                     }
             }
             __syncthreads();
+            // the pivot row in batches of QB 16-byte reads issued ahead of their
+            // FMAs, so that a batch's LDS latency is paid once
 #pragma unroll
-            for (int cl0 = 0; cl0 < H; cl0 += 2) {
-                if (H * CH + cl0 + 1 > k) {  // a column of the pair is still live
-                    const double2 u = *reinterpret_cast<const double2*>(prow + H * CH + cl0);
-                    if (H * CH + cl0 > k) row[cl0] = fma(-l, u.x, row[cl0]);
-                    row[cl0 + 1] = fma(-l, u.y, row[cl0 + 1]);
+            for (int cb = 0; cb < H; cb += 2 * QB) {
+                double2 u[QB];
+#pragma unroll
+                for (int b = 0; b < QB; ++b) {
+                    const int cl0 = cb + 2 * b;
+                    if (cl0 < H && H * CH + cl0 + 1 > k)  // a column of the pair is still live
+                        u[b] = *reinterpret_cast<const double2*>(prow + H * CH + cl0);
+                }
+#pragma unroll
+                for (int b = 0; b < QB; ++b) {
+                    const int cl0 = cb + 2 * b;
+                    if (cl0 < H && H * CH + cl0 + 1 > k) {
+                        if (H * CH + cl0 > k) row[cl0] = fma(-l, u[b].x, row[cl0]);
+                        row[cl0 + 1] = fma(-l, u[b].y, row[cl0 + 1]);
+                    }
                 }
             }
             if (CH == 0) {
