@@ -859,21 +859,22 @@ extern "C" rbf_status rbf_select_stencils(rbf_ctx* ctx, const double* X, int64_t
 // Ascending node ids inside every cell (the atomic ranks of the binning give an
 // arbitrary order): one thread per cell, insertion sort; cells above 256 nodes
 // (degenerate clusters) keep their order.
-__global__ __launch_bounds__(256) void k_sort_cells(const GridParams* __restrict__ gp,
-                                                    const int* __restrict__ cell_start, int32_t* __restrict__ ids) {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= gp->ncell) return;
+// Ascending ids inside each cell, whatever its size: the id at position p of
+// the cell-ordered array moves to the cell's start plus the number of ids of
+// its cell that are smaller (ids are distinct, so the ranks are a permutation of
+// the cell's positions).  One thread per position; work per cell is the square
+// of its size, spread over its threads.
+__global__ __launch_bounds__(256) void k_cell_rank(int64_t N, const int* __restrict__ cell_of,
+                                                   const int* __restrict__ cell_start, const int32_t* __restrict__ ids,
+                                                   int32_t* __restrict__ out) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= N) return;
+    const int32_t v = ids[p];
+    const int c = cell_of[v];
     const int a = cell_start[c], b = cell_start[c + 1];
-    if (b - a > 256) return;
-    for (int i = a + 1; i < b; ++i) {
-        const int32_t v = ids[i];
-        int j = i - 1;
-        while (j >= a && ids[j] > v) {
-            ids[j + 1] = ids[j];
-            --j;
-        }
-        ids[j + 1] = v;
-    }
+    int r = 0;
+    for (int i = a; i < b; ++i) r += ids[i] < v ? 1 : 0;
+    out[a + r] = v;
 }
 
 namespace rbf {
@@ -883,7 +884,8 @@ size_t cell_order_ws(int64_t N, int d) { return sel_layout(N, d).total; }
 
 // Node ids in the order of a uniform grid of cells holding about per_cell nodes
 // each (cells in x-fastest order, ascending ids within a cell): order[N]
-// (device).  Enqueued on s; ws (cell_order_ws bytes) is scratch.
+// (device), the same for every run.  Enqueued on s; ws (cell_order_ws bytes) is
+// scratch.
 hipError_t cell_order_enqueue(hipStream_t s, const double* X, int64_t N, int d, double per_cell, void* ws,
                               int32_t* order) {
     const SelWorkspace L = sel_layout(N, d);
@@ -905,8 +907,11 @@ hipError_t cell_order_enqueue(hipStream_t s, const double* X, int64_t N, int d, 
     hipLaunchKernelGGL(k_scan_blocks, dim3(L.nb_scan), dim3(256), 0, s, count, L.cap + 1, bsum);
     hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, L.nb_scan);
     hipLaunchKernelGGL(k_scan_apply, dim3(L.nb_scan), dim3(256), 0, s, count, L.cap + 1, bsum);
-    hipLaunchKernelGGL(k_bin_scatter, dim3(nbN), dim3(256), 0, s, X, N, d, count, cell_of, rank, order, sx);
-    hipLaunchKernelGGL(k_sort_cells, dim3((unsigned)((L.cap + 255) / 256)), dim3(256), 0, s, gp, count, order);
+    // the ids in cell order (any order inside a cell: the ranks are atomic) in the
+    // layout's sorted_id buffer, then in ascending order inside each cell to order
+    int32_t* ids = (int32_t*)(w + L.sorted_id);
+    hipLaunchKernelGGL(k_bin_scatter, dim3(nbN), dim3(256), 0, s, X, N, d, count, cell_of, rank, ids, sx);
+    hipLaunchKernelGGL(k_cell_rank, dim3(nbN), dim3(256), 0, s, N, cell_of, count, ids, order);
     return hipGetLastError();
 }
 

@@ -176,6 +176,44 @@ def test_block_jacobi_cuts_iterations(gpu, d, h, n):
     assert abs(eb - ej) <= 1e-3 * ej
 
 
+def test_block_jacobi_order_is_deterministic_with_a_crowded_cell(gpu):
+    """The node order of the block-Jacobi preconditioner is ascending ids inside
+    every cell, also in a cell far above the average fill (400 coincident-ish
+    nodes): two set-ups give the same bytes, the order is a permutation, and the
+    crowded cell's ids come out sorted."""
+    rb = _rb()
+    rng = np.random.default_rng(11)
+    X = np.concatenate([rng.random((3000, 2)), 0.5 + 1e-9 * rng.random((400, 2))])
+    perm_in = rng.permutation(X.shape[0])
+    X = np.ascontiguousarray(X[perm_in])
+    N = X.shape[0]
+    off = np.arange(N + 1, dtype=np.int64)
+    idx = np.arange(N, dtype=np.int32)
+    vals = np.full(N, 2.0)
+    T = [_t(a, gpu) for a in (X, off, idx, vals)]
+    pc1 = rb.block_jacobi(*T)
+    pc2 = rb.block_jacobi(*T)
+    # the order, its inverse, the float16 inverses and their scales (regions
+    # aligned to 256 bytes; the padding between them and the set-up's scratch
+    # at the end are not part of the result)
+    al = lambda b: (b + 255) // 256 * 256  # noqa: E731
+    nb = (N + 63) // 64
+    o = 0
+    for size in (4 * N, 4 * N, 2 * 64 * 64 * nb, 4 * 64 * nb):
+        assert torch.equal(pc1[o:o + size], pc2[o:o + size])
+        o += al(size)
+    order = pc1[: 4 * N].cpu().numpy().view(np.int32)
+    assert np.array_equal(np.sort(order), np.arange(N))
+    crowd = np.nonzero(perm_in >= 3000)[0]              # ids of the clustered nodes
+    pos = np.nonzero(np.isin(order, crowd))[0]
+    assert pos.max() - pos.min() + 1 >= 400
+    seg = order[pos.min():pos.max() + 1]
+    assert np.all(np.diff(seg) > 0)
+    # and the preconditioner solves the diagonal system exactly
+    x, info = rb.bicgstab(*T[1:], 1, _t(np.ones(N), gpu), tol=1e-12, precond="block_jacobi", pc=pc1)
+    assert info["status"] == rb.SOLVE_CONVERGED and np.allclose(x.cpu().numpy(), 0.5)
+
+
 def test_3d_neumann_reports_failure(gpu):
     """Closest-node Neumann rows in 3D: a few percent have a normal-derivative weight
     at the node of the wrong sign, the operator is unstable and no preconditioner
