@@ -1009,8 +1009,8 @@ def bench_poisson(a, torch, rb, B):
     vp, vs = ("k_bj_vec<P>", "k_bj_vec<S>") if bj else ("k_vec<P>", "k_vec<S>")
     res["roofline"] = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                        "frac": gbs / PEAK_HBM_GBS, "traffic": recorded_traffic(a.workload),
-                       "kernel": f"BiCGStab iteration ({vp}, k_spmv<V>, k_reduce, {vs}, k_spmv<T>, k_reduce, "
-                                 f"k_vec<X>, k_reduce; row products k_spmv<8,{(n + 7) // 8}>)",
+                       "kernel": f"BiCGStab iteration ({vp}, k_spmv<V>, {vs}, k_spmv<T>, k_vec<X>; "
+                                 f"row products k_spmv<8,{(n + 7) // 8}>)",
                        "bytes_per_row_per_iteration": per_row, "rows": N, "iterations": it}
     if not a.no_compare:
         # the other preconditioner on the same system, one untimed-by-the-step solve

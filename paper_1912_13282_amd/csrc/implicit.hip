@@ -15,23 +15,28 @@
 // into the p and s updates (one wavefront per block: an 8 KB inverse read
 // coalesced, the vector entries broadcast by lane reads).
 //
-// One BiCGStab iteration (van der Vorst 1992) on the scaled system
+// One BiCGStab iteration i (van der Vorst 1992) on the scaled system
 // A = D^-1 M, b = D^-1 r (D = I for the block form, whose products take
-// ph = P^-1 p and sh = P^-1 s, and whose x adds them):
-//     p = r + beta (p - omega v)          k_vec<P> | k_bj_vec<P>    beta = (rho / rho_prev)(alpha / omega)
-//     v = A p,  alpha = rho / (rh . v)    k_spmv<V>
-//     s = r - alpha v,  |s|^2             k_vec<S> | k_bj_vec<S>
-//     t = A s,  omega = (t . s)/(t . t)   k_spmv<T>    |s| small: omega = 0, done after the x update
-//     x += alpha p + omega s,  r = s - omega t,  rho = rh . r,  |r|^2      k_vec<X>
-// The scalars live in device memory.  Each dot product is summed per block in
-// a fixed order; a one-block kernel then adds the block sums, again in a fixed
-// order, and updates the scalars (k_reduce: after v, after t -- with |s|^2 --
-// and after x), so no kernel waits for the host and the result does not
-// depend on timing.  (Letting the last block of the
+// ph = P^-1 p and sh = P^-1 s, and whose x adds them), five launches:
+//     rho_i = rh . r, status; p = r + beta (p - omega v)     k_vec<P> | k_bj_vec<P>
+//         beta = (rho_i / rho_{i-1})(alpha / omega)
+//     v = A p,  rh . v                                       k_spmv<V>
+//     alpha = rho_i / (rh . v);  s = r - alpha v,  |s|^2     k_vec<S> | k_bj_vec<S>
+//     t = A s,  t . s,  t . t                                k_spmv<T>
+//     omega = (t . s)/(t . t) (0 if |s| is small: converged at the half step);
+//     x += alpha p + omega s,  r = s - omega t,  rh . r, |r|^2          k_vec<X>
+// Each dot product is summed per block in a fixed order; every block of the
+// kernel that needs the scalar adds the producing kernel's block sums itself,
+// in the same fixed order (so all blocks agree bit for bit), and block 0
+// records it in the device-side state for later kernels and the host.  No
+// kernel waits for the host and the result does not depend on timing.  A kernel
+// never reads a state field that its own block 0 writes (rho alternates between
+// two slots by iteration parity).  (Letting the last block of the
 // producing kernel do it would need a device-scope release per block, which
 // writes back the L2 of every XCD: far slower than the extra launch.)  Every
-// kernel returns at once when the solve has ended; the host checks the state
-// every CHECK_EVERY iterations.
+// kernel returns at once when the solve has ended.  The host enqueues
+// CHECK_EVERY iterations at a time, each chunk followed by one single-block
+// kernel that makes the next iteration's checks, and then reads the state.
 #include "cellorder.hpp"
 #include "rowdot.hpp"
 
@@ -91,7 +96,8 @@ static_assert(NBVEC <= NBMAX, "the vector kernels share the block sums of the ro
 constexpr int CHECK_EVERY = 16;  // iterations between host checks
 
 struct SolveState {
-    double rho, rho_prev, alpha, omega;
+    double rho[2];        // rho_i at [i & 1] (rho_0 = 1)
+    double alpha, omega;  // of the latest iteration
     double rr, bb, tol2, rr0;
     double true_rr, true_bb;
     int status, half, iter, max_iter;
@@ -114,8 +120,9 @@ struct SolveArgs {
     const double *xp, *xs;   // what the products take and x adds: p and s, or ph and sh
     const _Float16* binv;    // block-Jacobi (the system in block order): inverses, rows scaled, or NULL
     const float* bscale;     // block-Jacobi: the row scales
-    double* part;            // block sums of the row products and of x (two per block)
+    double* part;            // block sums of the row products (two per block)
     double* part_s;          // block sums of |s|^2 (one per block)
+    double* part_x;          // block sums of rh . r and |r|^2 of the x update (two per block)
     SolveState* st;
 };
 
@@ -138,7 +145,7 @@ __device__ __forceinline__ void block_partials(double (&v)[K], double* part) {
 
 __global__ void k_state_init(SolveState* st, int max_iter, double tol) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    st->rho = st->rho_prev = st->alpha = st->omega = 1.0;
+    st->rho[0] = st->rho[1] = st->alpha = st->omega = 1.0;
     st->rr = st->bb = st->rr0 = st->true_rr = st->true_bb = 0.0;
     st->tol2 = tol * tol;  // scaled by |b|^2 once that is known
     st->status = RUNNING;
@@ -276,49 +283,23 @@ __global__ __launch_bounds__(256) void k_spmv(SolveArgs a) {
     block_partials<2>(tot, a.part);
 }
 
-enum { VP, VS, VX };
+enum { RD_R0, RD_CHECK, RD_TRUE };
 
-//   VP: p = r + beta (p - omega v)
-//   VS: s = r - alpha v;  |s|^2 (half-step convergence, checked with omega)
-//   VX: x += alpha p + omega s;  r = s - omega t;  rho = rh . r, |r|^2
-template <int MODE>
-__global__ __launch_bounds__(256) void k_vec(SolveArgs a) {
-    SolveState* st = a.st;
-    if (st->status != RUNNING) return;
-    const double alpha = st->alpha, omega = st->omega;
-    const double beta = (st->rho / st->rho_prev) * (alpha / omega);
-    const int64_t N = a.N, stride = (int64_t)gridDim.x * blockDim.x;
-    double c0 = 0.0, c1 = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
-        if (MODE == VP) {
-            a.p[i] = a.r[i] + beta * (a.p[i] - omega * a.v[i]);
-        } else if (MODE == VS) {
-            const double si = a.r[i] - alpha * a.v[i];
-            a.s[i] = si;
-            c0 += si * si;
-        } else {
-            const double si = a.s[i];
-            a.x[i] += alpha * a.xp[i] + omega * a.xs[i];
-            const double ri = omega != 0.0 ? si - omega * a.t[i] : si;  // omega = 0: converged at s
-            a.r[i] = ri;
-            c0 += a.rh[i] * ri;
-            c1 += ri * ri;
-        }
-    }
-    if (MODE == VP) return;
-    if (MODE == VS) {
-        double tot[1] = {c0};
-        block_partials<1>(tot, a.part_s);
-    } else {
-        double tot[2] = {c0, c1};
-        block_partials<2>(tot, a.part);
-    }
+// Whether the solve is running, as one value for the whole block: block 0 of
+// the same kernel may record an outcome while other blocks start, and all
+// wavefronts of a block must take the same branch (the block sums use
+// barriers, and a wavefront that went on alone would act on partial sums).
+__device__ __forceinline__ bool block_running(const SolveState* st) {
+    __shared__ int s;
+    if (threadIdx.x == 0) s = st->status;
+    __syncthreads();
+    return s == RUNNING;
 }
 
-enum { RD_R0, RD_V, RD_T, RD_X, RD_TRUE };
-
 // Sums of the nb block sums part[b][0..1] and (S) the ns block sums ps[b], each
-// in a fixed order, by the whole block; the totals are valid in thread 0.
+// in a fixed order, by the whole block; the totals are valid in every thread
+// (all compute them from the same partial sums) and the function may be
+// called again in the same kernel.
 template <bool S>
 __device__ __forceinline__ void sum_parts(const double* part, int nb, const double* ps, int ns, double (&tot)[3]) {
     __shared__ double red[3][4];
@@ -351,23 +332,152 @@ __device__ __forceinline__ void sum_parts(const double* part, int nb, const doub
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < 3; ++c) tot[c] = (S || c < 2) ? (red[c][0] + red[c][1]) + (red[c][2] + red[c][3]) : 0.0;
+    __syncthreads();  // red may be written again
 }
 
-// Sum of the nb block sums (fixed order) and the scalar update of each step;
-// RD_T also sums the ns block sums of |s|^2.
-template <int MODE>
-__global__ __launch_bounds__(256) void k_reduce(SolveArgs a, int nb, int ns) {
+// Start of iteration it (> 1): rho_it = rh . r and |r|^2 of iteration it - 1
+// from the nbx block sums of its x update, and the end-of-iteration checks;
+// block 0 records rho_it, |r|^2, the iterations done and the outcome.  Every
+// thread of the calling block gets rho_it; false: the solve has ended.  Called
+// by every thread of a block that found the solve running.
+__device__ bool iteration_head(const SolveArgs& a, int it, int nbx, double& rho_it) {
     SolveState* st = a.st;
-    if (MODE != RD_R0 && MODE != RD_TRUE && st->status != RUNNING) return;
+    if (it <= 1) {  // from the initial residual
+        rho_it = st->rho[1];
+        return true;
+    }
+    double t[3];
+    sum_parts<false>(a.part_x, nbx, nullptr, 0, t);
+    const int done = it - 1;
+    int status = RUNNING;
+    if (st->half || t[1] <= st->tol2)
+        status = RBF_SOLVE_CONVERGED;
+    else if (!isfinite(t[0]) || !isfinite(t[1]))
+        status = RBF_SOLVE_BREAKDOWN;
+    else if (t[1] > DIVERGE2 * st->rr0)
+        status = RBF_SOLVE_DIVERGED;
+    else if (done >= st->max_iter)
+        status = RBF_SOLVE_MAXITER;
+    else if (t[0] == 0.0 || st->omega == 0.0)
+        status = RBF_SOLVE_BREAKDOWN;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->rho[it & 1] = t[0];
+        st->rr = t[1];
+        st->iter = done;
+        if (status != RUNNING) st->status = status;
+    }
+    rho_it = t[0];
+    return status == RUNNING;
+}
+
+// alpha = rho_it / (rh . v) from the nbv block sums of the row product v = A p;
+// block 0 records it or the breakdown.  Uniform; false: breakdown.
+__device__ bool half_step_alpha(const SolveArgs& a, int it, int nbv, double& alpha) {
+    double t[3];
+    sum_parts<false>(a.part, nbv, nullptr, 0, t);
+    const bool ok = t[0] != 0.0 && isfinite(t[0]);
+    alpha = ok ? a.st->rho[it & 1] / t[0] : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (ok)
+            a.st->alpha = alpha;
+        else
+            a.st->status = RBF_SOLVE_BREAKDOWN;
+    }
+    return ok;
+}
+
+// omega = (t . s) / (t . t) from the nbt block sums of t = A s, or 0 when |s|^2
+// (ns block sums) is within the tolerance (converged at the half step); block 0
+// records omega and the half flag or the breakdown.  Uniform; false: breakdown.
+__device__ bool full_step_omega(const SolveArgs& a, int nbt, int ns, double& omega) {
+    SolveState* st = a.st;
+    double t[3];
+    sum_parts<true>(a.part, nbt, a.part_s, ns, t);
+    const bool half = t[2] <= st->tol2;
+    const bool ok = half || (t[1] > 0.0 && isfinite(t[0]) && isfinite(t[1]));
+    omega = half ? 0.0 : (ok ? t[0] / t[1] : 0.0);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (!ok) {
+            st->status = RBF_SOLVE_BREAKDOWN;
+        } else {
+            st->omega = omega;
+            if (half) st->half = 1;
+        }
+    }
+    return ok;
+}
+
+enum { VP, VS, VX };
+
+// Vector passes of iteration it; nb (and ns) count the block sums of the
+// kernel(s) before, whose scalars they finish (see the header comment):
+//   VP: head of the iteration, p = r + beta (p - omega v)
+//   VS: alpha;  s = r - alpha v;  |s|^2
+//   VX: omega;  x += alpha p + omega s;  r = s - omega t;  rh . r, |r|^2
+template <int MODE>
+__global__ __launch_bounds__(256) void k_vec(SolveArgs a, int it, int nb, int ns) {
+    SolveState* st = a.st;
+    if (!block_running(st)) return;
+    double alpha = 0.0, omega = 0.0, beta = 0.0;
+    if (MODE == VP) {
+        double rho_it;
+        if (!iteration_head(a, it, nb, rho_it)) return;
+        omega = st->omega;
+        beta = (rho_it / st->rho[(it - 1) & 1]) * (st->alpha / omega);
+    } else if (MODE == VS) {
+        if (!half_step_alpha(a, it, nb, alpha)) return;
+    } else {
+        alpha = st->alpha;
+        if (!full_step_omega(a, nb, ns, omega)) return;
+    }
+    const int64_t N = a.N, stride = (int64_t)gridDim.x * blockDim.x;
+    double c0 = 0.0, c1 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+        if (MODE == VP) {
+            a.p[i] = a.r[i] + beta * (a.p[i] - omega * a.v[i]);
+        } else if (MODE == VS) {
+            const double si = a.r[i] - alpha * a.v[i];
+            a.s[i] = si;
+            c0 += si * si;
+        } else {
+            const double si = a.s[i];
+            a.x[i] += alpha * a.xp[i] + omega * a.xs[i];
+            const double ri = omega != 0.0 ? si - omega * a.t[i] : si;  // omega = 0: converged at s
+            a.r[i] = ri;
+            c0 += a.rh[i] * ri;
+            c1 += ri * ri;
+        }
+    }
+    if (MODE == VP) return;
+    if (MODE == VS) {
+        double tot[1] = {c0};
+        block_partials<1>(tot, a.part_s);
+    } else {
+        double tot[2] = {c0, c1};
+        block_partials<2>(tot, a.part_x);
+    }
+}
+
+// Sum of the nb block sums (fixed order) and the scalar update of the steps
+// outside the iteration: the start (RD_R0), the end-of-chunk check of iteration
+// it (RD_CHECK, what the next iteration's head would record), and the residual
+// of the result (RD_TRUE).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_reduce(SolveArgs a, int nb, int it) {
+    SolveState* st = a.st;
+    if (MODE == RD_CHECK) {
+        double rho_it;
+        if (block_running(st)) iteration_head(a, it, nb, rho_it);
+        return;
+    }
     double tot[3];
-    sum_parts<MODE == RD_T>(a.part, nb, a.part_s, ns, tot);
-    const double ss[1] = {tot[2]};
+    sum_parts<false>(a.part, nb, nullptr, 0, tot);
     if (threadIdx.x != 0) return;
     if (MODE == RD_R0) {
         st->rr = tot[0];
         st->rr0 = tot[0];
         st->bb = tot[1];
-        st->rho = tot[0];
+        st->rho[1] = tot[0];
         // relative to |b|; a zero right-hand side is measured against the start
         st->tol2 = st->tol2 * (tot[1] > 0.0 ? tot[1] : tot[0]);
         if (st->baddiag)
@@ -378,35 +488,6 @@ __global__ __launch_bounds__(256) void k_reduce(SolveArgs a, int nb, int ns) {
             st->status = RBF_SOLVE_CONVERGED;
         else if (st->max_iter <= 0)
             st->status = RBF_SOLVE_MAXITER;
-    } else if (MODE == RD_V) {
-        if (!(tot[0] != 0.0) || !isfinite(tot[0]))
-            st->status = RBF_SOLVE_BREAKDOWN;
-        else
-            st->alpha = st->rho / tot[0];
-    } else if (MODE == RD_T) {
-        if (ss[0] <= st->tol2) {  // converged at the half step: x += alpha p
-            st->half = 1;
-            st->omega = 0.0;
-        } else if (!(tot[1] > 0.0) || !isfinite(tot[0]) || !isfinite(tot[1]))
-            st->status = RBF_SOLVE_BREAKDOWN;
-        else
-            st->omega = tot[0] / tot[1];
-    } else if (MODE == RD_X) {
-        const double omega = st->omega;
-        st->rho_prev = st->rho;
-        st->rho = tot[0];
-        st->rr = tot[1];
-        st->iter += 1;
-        if (st->half || tot[1] <= st->tol2)
-            st->status = RBF_SOLVE_CONVERGED;
-        else if (!isfinite(tot[1]) || !isfinite(tot[0]))
-            st->status = RBF_SOLVE_BREAKDOWN;
-        else if (tot[1] > DIVERGE2 * st->rr0)
-            st->status = RBF_SOLVE_DIVERGED;
-        else if (st->iter >= st->max_iter)
-            st->status = RBF_SOLVE_MAXITER;
-        else if (tot[0] == 0.0 || omega == 0.0)
-            st->status = RBF_SOLVE_BREAKDOWN;
     } else {
         st->true_rr = tot[0];
         st->true_bb = tot[1];
@@ -547,22 +628,30 @@ __global__ __launch_bounds__(256) void k_bj_setup(int64_t N, const int64_t* __re
 }
 
 // The p and s updates of the block form (the system in block order, one
-// wavefront per node block), each followed by its block product:
+// wavefront per node block), each followed by its block product (the scalars
+// as in k_vec: iteration head before p, alpha before s):
 //   S = false:  p = r + beta (p - omega v),  ph = P^-1 p
 //   S = true:   s = r - alpha v,  sh = P^-1 s,  |s|^2
 // Row k of a block product is scale_k * sum_j h_kj y_j in float64 over the
 // float16 entries h_kj; y_j comes from lane j by lane reads.
 template <bool S>
-__global__ __launch_bounds__(256) void k_bj_vec(SolveArgs a) {
+__global__ __launch_bounds__(256) void k_bj_vec(SolveArgs a, int it, int nb) {
     SolveState* st = a.st;
-    if (st->status != RUNNING) return;
-    const double alpha = st->alpha, omega = st->omega;
-    const double beta = (st->rho / st->rho_prev) * (alpha / omega);
+    if (!block_running(st)) return;
+    double alpha = 0.0, omega = 0.0, beta = 0.0;
+    if (S) {
+        if (!half_step_alpha(a, it, nb, alpha)) return;
+    } else {
+        double rho_it;
+        if (!iteration_head(a, it, nb, rho_it)) return;
+        omega = st->omega;
+        beta = (rho_it / st->rho[(it - 1) & 1]) * (st->alpha / omega);
+    }
     const int lane = lane_id();
-    const int64_t nb = (a.N + BJ - 1) / BJ;
+    const int64_t nblk = (a.N + BJ - 1) / BJ;
     const int64_t nw = (int64_t)gridDim.x * 4;
     double c0 = 0.0;
-    for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < nb; b += nw) {
+    for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < nblk; b += nw) {
         const int64_t q = b * BJ + lane;
         const bool in = q < a.N;
         double y = 0.0;
@@ -610,7 +699,9 @@ struct DiagL {
 // the solver kernels with rows of at most n_max entries
 template <int G, int E, int U>
 struct SolverL {
-    static hipError_t launch(hipStream_t s, SolveArgs a, int what) {
+    // what: 0 start, 1 iteration it, 2 end-of-chunk check before iteration it,
+    // 3 residual of the result
+    static hipError_t launch(hipStream_t s, SolveArgs a, int what, int it) {
         const dim3 gr(blocks_for(a.N * G, NBMAX)), gv(blocks_for(a.N, NBVEC)), b(256), one(1);
         // one wavefront per node block, at most NBVEC blocks (the |s|^2 block sums)
         const dim3 gb(blocks_for(((a.N + BJ - 1) / BJ) * 64, NBVEC));
@@ -622,19 +713,19 @@ struct SolverL {
                 break;
             case 1:
                 if (a.binv)
-                    hipLaunchKernelGGL((k_bj_vec<false>), gb, b, 0, s, a);
+                    hipLaunchKernelGGL((k_bj_vec<false>), gb, b, 0, s, a, it, nv);
                 else
-                    hipLaunchKernelGGL((k_vec<VP>), gv, b, 0, s, a);
+                    hipLaunchKernelGGL((k_vec<VP>), gv, b, 0, s, a, it, nv, 0);
                 hipLaunchKernelGGL((k_spmv<G, E, U, SP_V>), gr, b, 0, s, a);
-                hipLaunchKernelGGL((k_reduce<RD_V>), one, b, 0, s, a, nr, 0);
                 if (a.binv)
-                    hipLaunchKernelGGL((k_bj_vec<true>), gb, b, 0, s, a);
+                    hipLaunchKernelGGL((k_bj_vec<true>), gb, b, 0, s, a, it, nr);
                 else
-                    hipLaunchKernelGGL((k_vec<VS>), gv, b, 0, s, a);
+                    hipLaunchKernelGGL((k_vec<VS>), gv, b, 0, s, a, it, nr, 0);
                 hipLaunchKernelGGL((k_spmv<G, E, U, SP_T>), gr, b, 0, s, a);
-                hipLaunchKernelGGL((k_reduce<RD_T>), one, b, 0, s, a, nr, ns);
-                hipLaunchKernelGGL((k_vec<VX>), gv, b, 0, s, a);
-                hipLaunchKernelGGL((k_reduce<RD_X>), one, b, 0, s, a, nv, 0);
+                hipLaunchKernelGGL((k_vec<VX>), gv, b, 0, s, a, it, nr, ns);
+                break;
+            case 2:
+                hipLaunchKernelGGL((k_reduce<RD_CHECK>), one, b, 0, s, a, nv, it);
                 break;
             default:
                 hipLaunchKernelGGL((k_spmv<G, E, U, SP_TRUE>), gr, b, 0, s, a);
@@ -648,27 +739,27 @@ struct SolverL {
 // Row-product shape of the solver (measured on 1M-row systems): two lanes per
 // row for rows of at most 10 entries, eight lanes with two rows in flight up
 // to 64, then 16 and 64 lanes.  Longer rows than n_max are still summed whole.
-hipError_t solver_launch(int n_max, hipStream_t s, SolveArgs a, int what) {
+hipError_t solver_launch(int n_max, hipStream_t s, SolveArgs a, int what, int it = 0) {
     switch (n_max <= 10 ? (n_max + 1) / 2 : 0) {
-        case 1: return SolverL<2, 1, 1>::launch(s, a, what);
-        case 2: return SolverL<2, 2, 1>::launch(s, a, what);
-        case 3: return SolverL<2, 3, 1>::launch(s, a, what);
-        case 4: return SolverL<2, 4, 1>::launch(s, a, what);
-        case 5: return SolverL<2, 5, 1>::launch(s, a, what);
+        case 1: return SolverL<2, 1, 1>::launch(s, a, what, it);
+        case 2: return SolverL<2, 2, 1>::launch(s, a, what, it);
+        case 3: return SolverL<2, 3, 1>::launch(s, a, what, it);
+        case 4: return SolverL<2, 4, 1>::launch(s, a, what, it);
+        case 5: return SolverL<2, 5, 1>::launch(s, a, what, it);
         default: break;
     }
     switch (n_max <= 64 ? (n_max + 7) / 8 : 0) {
-        case 2: return SolverL<8, 2, 2>::launch(s, a, what);
-        case 3: return SolverL<8, 3, 2>::launch(s, a, what);
-        case 4: return SolverL<8, 4, 2>::launch(s, a, what);
-        case 5: return SolverL<8, 5, 2>::launch(s, a, what);
-        case 6: return SolverL<8, 6, 2>::launch(s, a, what);
-        case 7: return SolverL<8, 7, 2>::launch(s, a, what);
-        case 8: return SolverL<8, 8, 2>::launch(s, a, what);
+        case 2: return SolverL<8, 2, 2>::launch(s, a, what, it);
+        case 3: return SolverL<8, 3, 2>::launch(s, a, what, it);
+        case 4: return SolverL<8, 4, 2>::launch(s, a, what, it);
+        case 5: return SolverL<8, 5, 2>::launch(s, a, what, it);
+        case 6: return SolverL<8, 6, 2>::launch(s, a, what, it);
+        case 7: return SolverL<8, 7, 2>::launch(s, a, what, it);
+        case 8: return SolverL<8, 8, 2>::launch(s, a, what, it);
         default: break;
     }
-    if (n_max <= 128) return SolverL<16, 8, 1>::launch(s, a, what);
-    return SolverL<64, 4, 1>::launch(s, a, what);
+    if (n_max <= 128) return SolverL<16, 8, 1>::launch(s, a, what, it);
+    return SolverL<64, 4, 1>::launch(s, a, what, it);
 }
 
 // ------------------------------------------------------------------ block order
@@ -806,7 +897,7 @@ __global__ __launch_bounds__(256) void k_perm_vec(int64_t N, const int32_t* __re
 }
 
 struct SolveLayout {
-    size_t st, part, part_s, vec[9], poff, pidx, pvals, pb, px, bsum, total;
+    size_t st, part, part_s, part_x, vec[9], poff, pidx, pvals, pb, px, bsum, total;
 };
 
 SolveLayout solve_layout(int64_t N, int64_t nnz, bool bj) {
@@ -818,6 +909,8 @@ SolveLayout solve_layout(int64_t N, int64_t nnz, bool bj) {
     o += rbf_align((size_t)NBMAX * 2 * sizeof(double));
     L.part_s = o;
     o += rbf_align((size_t)NBVEC * sizeof(double));
+    L.part_x = o;
+    o += rbf_align((size_t)NBVEC * 2 * sizeof(double));
     for (size_t& v : L.vec) {
         v = o;
         o += rbf_align((size_t)N * sizeof(double));
@@ -935,6 +1028,7 @@ extern "C" rbf_status rbf_bicgstab(rbf_ctx* ctx, int64_t N, const int64_t* offse
     a.st = (SolveState*)(w + WL.st);
     a.part = (double*)(w + WL.part);
     a.part_s = (double*)(w + WL.part_s);
+    a.part_x = (double*)(w + WL.part_x);
     double** vecs[9] = {&a.dinv, &a.r, &a.rh, &a.p, &a.v, &a.s, &a.t, &a.ph, &a.sh};
     for (int k = 0; k < 9; ++k) *vecs[k] = (double*)(w + WL.vec[k]);
     const int32_t* perm = nullptr;
@@ -980,6 +1074,8 @@ extern "C" rbf_status rbf_bicgstab(rbf_ctx* ctx, int64_t N, const int64_t* offse
         return RBF_EHIP;
     if (solver_launch(n_max, s, a, 0) != hipSuccess) return RBF_EHIP;
 
+    // iterations 1, 2, ... in chunks; after each chunk the checks that the next
+    // iteration's head would make (iteration max_iter + 1 is never launched)
     SolveState hs;
     int enqueued = 0;
     for (;;) {
@@ -988,10 +1084,11 @@ extern "C" rbf_status rbf_bicgstab(rbf_ctx* ctx, int64_t N, const int64_t* offse
         if (hs.status != RUNNING || enqueued >= max_iter) break;
         const int chunk = max_iter - enqueued < CHECK_EVERY ? max_iter - enqueued : CHECK_EVERY;
         for (int k = 0; k < chunk; ++k)
-            if (solver_launch(n_max, s, a, 1) != hipSuccess) return RBF_EHIP;
+            if (solver_launch(n_max, s, a, 1, enqueued + k + 1) != hipSuccess) return RBF_EHIP;
         enqueued += chunk;
+        if (solver_launch(n_max, s, a, 2, enqueued + 1) != hipSuccess) return RBF_EHIP;
     }
-    if (solver_launch(n_max, s, a, 2) != hipSuccess) return RBF_EHIP;
+    if (solver_launch(n_max, s, a, 3) != hipSuccess) return RBF_EHIP;
     if (bj)
         hipLaunchKernelGGL((k_perm_vec<false>), dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, N, perm,
                            (const double*)a.x, x, (const double*)nullptr, (double*)nullptr);
