@@ -394,7 +394,11 @@ typedef struct rbf_solve_info {
  * the same M), and stops when ||r - M x|| <= tol ||r||; it copies M, r and x
  * into the node order of pc inside the workspace (x is copied back on return),
  * so its iterations read every vector contiguously.  pc/pc_bytes are ignored by
- * the other preconditioners (may be NULL).  Any form also stops
+ * the other preconditioners (may be NULL).  The monitored residual is updated
+ * by the recursion; once it meets tol, the residual is recomputed from x in the
+ * same norm and, if that exceeds 2 tol, the iteration restarts from x (at
+ * most 3 times; iterations counts all of them; after the last restart the
+ * monitored residual decides).  Any form also stops
  * after max_iter iterations, or with RBF_SOLVE_DIVERGED once the monitored
  * residual exceeds 10^6 times its initial value.  Every step runs on the
  * device (no host round trip inside an iteration); the call waits for the

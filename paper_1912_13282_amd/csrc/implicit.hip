@@ -37,6 +37,9 @@
 // kernel returns at once when the solve has ended.  The host enqueues
 // CHECK_EVERY iterations at a time, each chunk followed by one single-block
 // kernel that makes the next iteration's checks, and then reads the state.
+// When the recursively updated residual has converged, the residual of x is
+// computed afresh (the two drift apart by rounding over many iterations) and
+// the iteration restarts from x if that one is above twice the tolerance.
 #include "cellorder.hpp"
 #include "rowdot.hpp"
 
@@ -102,10 +105,17 @@ struct SolveState {
     double true_rr, true_bb;
     int status, half, iter, max_iter;
     int baddiag;
+    int iter_base;  // iterations done before the latest restart
+    int verified;   // convergence confirmed by a recomputed residual
 };
 
 // A residual grown 10^6 times past the initial one ends the solve as DIVERGED.
 constexpr double DIVERGE2 = 1e12;
+// On convergence the residual is recomputed from x; above RESTART_SLACK times
+// the tolerance the iteration restarts from x, at most MAX_RESTARTS times (the
+// recursively updated residual drifts from b - M x by rounding).
+constexpr double RESTART_SLACK2 = 4.0;  // squared
+constexpr int MAX_RESTARTS = 3;
 
 struct SolveArgs {
     int64_t N;
@@ -143,6 +153,30 @@ __device__ __forceinline__ void block_partials(double (&v)[K], double* part) {
         for (int q = 0; q < K; ++q) part[(size_t)blockIdx.x * K + q] = (red[q][0] + red[q][1]) + (red[q][2] + red[q][3]);
 }
 
+// Grid-stride work split by XCD.  The hardware hands workgroups to the eight
+// XCDs in turn (workgroup b to XCD b mod 8), each with its own L2.  When the
+// grid is a multiple of eight, the workgroups of XCD x take part x of the items
+// (contiguous, a multiple of `align` long), so the vector entries a row
+// product gathers, and the rows that the next pass reads, stay within the L2
+// of one XCD instead of being fetched by all eight.  per_block items per
+// workgroup and pass; this thread's (or lane group's) items are first,
+// first + stride, ... below hi.
+struct XcdSplit {
+    int64_t first, hi, stride;
+};
+__device__ __forceinline__ XcdSplit xcd_split(int64_t n, int64_t align, int per_block, int sub) {
+    const int nx = (gridDim.x % 8 == 0) ? 8 : 1;
+    const int x = (int)(blockIdx.x % nx), lb = (int)(blockIdx.x / nx), lg = (int)(gridDim.x / nx);
+    int64_t part = (n + nx - 1) / nx;
+    part = (part + align - 1) / align * align;
+    const int64_t lo = min(n, (int64_t)x * part);
+    XcdSplit r;
+    r.hi = min(n, lo + part);
+    r.first = lo + (int64_t)lb * per_block + sub;
+    r.stride = (int64_t)lg * per_block;
+    return r;
+}
+
 __global__ void k_state_init(SolveState* st, int max_iter, double tol) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     st->rho[0] = st->rho[1] = st->alpha = st->omega = 1.0;
@@ -153,6 +187,8 @@ __global__ void k_state_init(SolveState* st, int max_iter, double tol) {
     st->iter = 0;
     st->max_iter = max_iter;
     st->baddiag = 0;
+    st->iter_base = 0;
+    st->verified = 0;
 }
 
 // dinv[i] = 1 / M[i][i] (Jacobi) or 1; a missing, zero or non-finite diagonal
@@ -198,17 +234,18 @@ __global__ __launch_bounds__(256) void k_spmv(SolveArgs a) {
     }
     const double* xin = MODE == SP_V ? a.xp : (MODE == SP_T ? a.xs : a.x);
     const int gl = threadIdx.x & (G - 1);
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x / G;
+    const XcdSplit xs = xcd_split(a.N, 64, 256 / G, threadIdx.x / G);
+    const int64_t stride = xs.stride;
     double c0 = 0.0, c1 = 0.0;
     // U rows (row0, row0 + stride, ...) per pass: their loads are in flight together
-    for (int64_t row0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / G; row0 < a.N; row0 += U * stride) {
+    for (int64_t row0 = xs.first; row0 < xs.hi; row0 += U * stride) {
         int64_t off[U], n[U];
         bool bad[U];
         double acc[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t row = row0 + u * stride;
-            const bool in = row < a.N;
+            const bool in = row < xs.hi;
             const int64_t o = in ? a.offsets[row] : 0, e = in ? a.offsets[row + 1] : 0;
             bad[u] = o < 0 || e < o || e > a.nnz;
             off[u] = o;
@@ -247,7 +284,7 @@ __global__ __launch_bounds__(256) void k_spmv(SolveArgs a) {
             const bool rbad = group_any<G>(bad[u]);
             double ax = group_sum<G>(acc[u]);
             if (rbad) ax = kNaN;
-            if (gl != 0 || row >= a.N) continue;
+            if (gl != 0 || row >= xs.hi) continue;
             if (MODE == SP_R0) {
                 const double di = a.dinv[row], bi = a.b[row];
                 const double ri = di * (bi - ax);
@@ -283,7 +320,7 @@ __global__ __launch_bounds__(256) void k_spmv(SolveArgs a) {
     block_partials<2>(tot, a.part);
 }
 
-enum { RD_R0, RD_CHECK, RD_TRUE };
+enum { RD_R0, RD_CHECK, RD_TRUE, RD_RESTART };
 
 // Whether the solve is running, as one value for the whole block: block 0 of
 // the same kernel may record an outcome while other blocks start, and all
@@ -335,7 +372,8 @@ __device__ __forceinline__ void sum_parts(const double* part, int nb, const doub
     __syncthreads();  // red may be written again
 }
 
-// Start of iteration it (> 1): rho_it = rh . r and |r|^2 of iteration it - 1
+// Start of iteration it (> 1, counted from the latest start or restart):
+// rho_it = rh . r and |r|^2 of iteration it - 1
 // from the nbx block sums of its x update, and the end-of-iteration checks;
 // block 0 records rho_it, |r|^2, the iterations done and the outcome.  Every
 // thread of the calling block gets rho_it; false: the solve has ended.  Called
@@ -348,7 +386,7 @@ __device__ bool iteration_head(const SolveArgs& a, int it, int nbx, double& rho_
     }
     double t[3];
     sum_parts<false>(a.part_x, nbx, nullptr, 0, t);
-    const int done = it - 1;
+    const int done = st->iter_base + it - 1;
     int status = RUNNING;
     if (st->half || t[1] <= st->tol2)
         status = RBF_SOLVE_CONVERGED;
@@ -430,9 +468,9 @@ __global__ __launch_bounds__(256) void k_vec(SolveArgs a, int it, int nb, int ns
         alpha = st->alpha;
         if (!full_step_omega(a, nb, ns, omega)) return;
     }
-    const int64_t N = a.N, stride = (int64_t)gridDim.x * blockDim.x;
+    const XcdSplit xs = xcd_split(a.N, 64, 256, threadIdx.x);
     double c0 = 0.0, c1 = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += stride) {
+    for (int64_t i = xs.first; i < xs.hi; i += xs.stride) {
         if (MODE == VP) {
             a.p[i] = a.r[i] + beta * (a.p[i] - omega * a.v[i]);
         } else if (MODE == VS) {
@@ -460,8 +498,9 @@ __global__ __launch_bounds__(256) void k_vec(SolveArgs a, int it, int nb, int ns
 
 // Sum of the nb block sums (fixed order) and the scalar update of the steps
 // outside the iteration: the start (RD_R0), the end-of-chunk check of iteration
-// it (RD_CHECK, what the next iteration's head would record), and the residual
-// of the result (RD_TRUE).
+// it (RD_CHECK, what the next iteration's head would record), the check of a
+// converged x and the restart from it (RD_RESTART), and the residual of the
+// result (RD_TRUE).
 template <int MODE>
 __global__ __launch_bounds__(256) void k_reduce(SolveArgs a, int nb, int it) {
     SolveState* st = a.st;
@@ -484,10 +523,27 @@ __global__ __launch_bounds__(256) void k_reduce(SolveArgs a, int nb, int it) {
             st->status = RBF_SOLVE_BADDIAG;
         else if (!isfinite(tot[0]) || !isfinite(tot[1]))
             st->status = RBF_SOLVE_BREAKDOWN;
-        else if (tot[0] <= st->tol2)
+        else if (tot[0] <= st->tol2) {
             st->status = RBF_SOLVE_CONVERGED;
-        else if (st->max_iter <= 0)
+            st->verified = 1;
+        } else if (st->max_iter <= 0) {
             st->status = RBF_SOLVE_MAXITER;
+        }
+    } else if (MODE == RD_RESTART) {
+        // the residual recomputed from x after the recursion reported convergence
+        // (r, rh, p, v, s, t already reset by the row product)
+        if (!isfinite(tot[0])) {
+            st->status = RBF_SOLVE_BREAKDOWN;
+        } else if (tot[0] <= RESTART_SLACK2 * st->tol2) {
+            st->verified = 1;  // stays converged, with the monitored residual
+        } else {
+            st->rr = tot[0];
+            st->rho[1] = tot[0];
+            st->rho[0] = st->alpha = st->omega = 1.0;
+            st->half = 0;
+            st->iter_base = st->iter;
+            st->status = RUNNING;
+        }
     } else {
         st->true_rr = tot[0];
         st->true_bb = tot[1];
@@ -648,10 +704,11 @@ __global__ __launch_bounds__(256) void k_bj_vec(SolveArgs a, int it, int nb) {
         beta = (rho_it / st->rho[(it - 1) & 1]) * (st->alpha / omega);
     }
     const int lane = lane_id();
-    const int64_t nblk = (a.N + BJ - 1) / BJ;
-    const int64_t nw = (int64_t)gridDim.x * 4;
+    // node blocks split by XCD as the rows of the other passes (parts of
+    // ceil(N / 512) blocks = ceil(N / 8) rows rounded up to 64)
+    const XcdSplit xs = xcd_split((a.N + BJ - 1) / BJ, 1, 4, threadIdx.x >> 6);
     double c0 = 0.0;
-    for (int64_t b = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); b < nblk; b += nw) {
+    for (int64_t b = xs.first; b < xs.hi; b += xs.stride) {
         const int64_t q = b * BJ + lane;
         const bool in = q < a.N;
         double y = 0.0;
@@ -683,8 +740,11 @@ __global__ __launch_bounds__(256) void k_bj_vec(SolveArgs a, int it, int nb) {
     }
 }
 
+// workgroups of 256 threads for `threads`, at most cap (a multiple of 8); from
+// 64 on a multiple of 8, so the work splits by XCD
 unsigned blocks_for(int64_t threads, int64_t cap) {
-    const int64_t b = (threads + 255) / 256;
+    int64_t b = (threads + 255) / 256;
+    if (b >= 64) b = (b + 7) / 8 * 8;
     return (unsigned)(b < cap ? (b > 0 ? b : 1) : cap);
 }
 
@@ -700,7 +760,7 @@ struct DiagL {
 template <int G, int E, int U>
 struct SolverL {
     // what: 0 start, 1 iteration it, 2 end-of-chunk check before iteration it,
-    // 3 residual of the result
+    // 3 residual of the result, 4 check of a converged x (restart)
     static hipError_t launch(hipStream_t s, SolveArgs a, int what, int it) {
         const dim3 gr(blocks_for(a.N * G, NBMAX)), gv(blocks_for(a.N, NBVEC)), b(256), one(1);
         // one wavefront per node block, at most NBVEC blocks (the |s|^2 block sums)
@@ -726,6 +786,10 @@ struct SolverL {
                 break;
             case 2:
                 hipLaunchKernelGGL((k_reduce<RD_CHECK>), one, b, 0, s, a, nv, it);
+                break;
+            case 4:
+                hipLaunchKernelGGL((k_spmv<G, E, U, SP_R0>), gr, b, 0, s, a);
+                hipLaunchKernelGGL((k_reduce<RD_RESTART>), one, b, 0, s, a, nr, 0);
                 break;
             default:
                 hipLaunchKernelGGL((k_spmv<G, E, U, SP_TRUE>), gr, b, 0, s, a);
@@ -1074,19 +1138,31 @@ extern "C" rbf_status rbf_bicgstab(rbf_ctx* ctx, int64_t N, const int64_t* offse
         return RBF_EHIP;
     if (solver_launch(n_max, s, a, 0) != hipSuccess) return RBF_EHIP;
 
-    // iterations 1, 2, ... in chunks; after each chunk the checks that the next
-    // iteration's head would make (iteration max_iter + 1 is never launched)
+    // iterations 1, 2, ... (counted from the latest start) in chunks; after each
+    // chunk the checks that the next iteration's head would make (no iteration
+    // past max_iter in all is launched).  A converged x is checked against its
+    // recomputed residual and, if that is above twice the tolerance, restarted from.
     SolveState hs;
-    int enqueued = 0;
+    int enqueued = 0, restarts = 0;
     for (;;) {
         RBF_HIP_CHECK(hipMemcpyAsync(&hs, a.st, sizeof(hs), hipMemcpyDeviceToHost, s));
         RBF_HIP_CHECK(hipStreamSynchronize(s));
-        if (hs.status != RUNNING || enqueued >= max_iter) break;
-        const int chunk = max_iter - enqueued < CHECK_EVERY ? max_iter - enqueued : CHECK_EVERY;
-        for (int k = 0; k < chunk; ++k)
-            if (solver_launch(n_max, s, a, 1, enqueued + k + 1) != hipSuccess) return RBF_EHIP;
-        enqueued += chunk;
-        if (solver_launch(n_max, s, a, 2, enqueued + 1) != hipSuccess) return RBF_EHIP;
+        const int left = max_iter - hs.iter_base - enqueued;
+        if (hs.status == RUNNING && left > 0) {
+            const int chunk = left < CHECK_EVERY ? left : CHECK_EVERY;
+            for (int k = 0; k < chunk; ++k)
+                if (solver_launch(n_max, s, a, 1, enqueued + k + 1) != hipSuccess) return RBF_EHIP;
+            enqueued += chunk;
+            if (solver_launch(n_max, s, a, 2, enqueued + 1) != hipSuccess) return RBF_EHIP;
+            continue;
+        }
+        if (hs.status == RBF_SOLVE_CONVERGED && !hs.verified && restarts < MAX_RESTARTS) {
+            if (solver_launch(n_max, s, a, 4) != hipSuccess) return RBF_EHIP;
+            ++restarts;
+            enqueued = 0;
+            continue;
+        }
+        break;
     }
     if (solver_launch(n_max, s, a, 3) != hipSuccess) return RBF_EHIP;
     if (bj)

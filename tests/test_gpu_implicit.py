@@ -128,11 +128,13 @@ def test_bicgstab_parity_with_direct_solve(gpu, d, precond, neumann):
                           precond=precond, pc=pc)
     assert info["status"] == rb.SOLVE_CONVERGED, info
     xh = x.cpu().numpy()
-    # the monitored (recursively updated) residual and the true one agree to rounding;
-    # over the thousand-odd iterations of the Neumann problem the recursion drifts
-    # further from b - M x at this tolerance (the true residual is reported in info)
+    # the monitored residual is updated by the recursion, which drifts from
+    # b - M x over the thousand-odd iterations of the Neumann problem; a converged
+    # x is checked against its recomputed residual (in the monitored norm) and
+    # restarted from when that is above 2 tol, so the recomputed residual here
+    # is within 2 tol up to the rounding of forming it
     res = _scaled_residual(off, idx, vals, rhs, xh, jacobi=precond == "jacobi")
-    assert res <= (30 if precond == "block_jacobi" else 10) * tol, (res, info)
+    assert res <= 2.5 * tol, (res, info)
     assert info["residual"] <= tol
     M = implicit.matrix(off, idx, vals)
     # the unscaled residual recomputed on the host, to the rounding of forming r - M x
