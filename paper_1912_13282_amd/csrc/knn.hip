@@ -9,9 +9,10 @@
 //   k_bin_count                   : cell of every node + rank inside its cell
 //   k_scan_*                      : exclusive scan of the cell counts
 //   k_bin_scatter                 : node ids and SoA coordinates in cell order
+//   k_knn_radius_group<QW, SPL>   : 64 / QW query nodes per wavefront (n_i <= 41):
 //   k_knn_radius                  : one wavefront per query node (n_i <= 101):
 //       every node within a radius estimated from the local density is
-//       filtered by its key, the survivors compacted in LDS and sorted once on
+//       filtered by its key, the survivors compacted in LDS and ordered once on
 //       (key, index) (exact: at least k survivors prove the radius sufficient)
 //   k_knn<T>, k_knn_list          : one wavefront per query node, n_i <= 129
 //       (and the queries the radius search leaves unsettled): candidates of the surrounding
@@ -745,6 +746,188 @@ __global__ __launch_bounds__(256) void k_knn_radius(const GridParams* __restrict
     }
 }
 
+// Several queries per wavefront for stencils of up to 41 nodes, the same search
+// and result as k_knn_radius: each query has a group of QW lanes (16 or 32),
+// with its own rows of cells, prefix sums and survivor buffer, so the
+// per-query set-up (density, radius, rows) runs once for 64 / QW queries.
+// Survivors are capped at QW * SPL (SPL per lane) and ordered by counting
+// ranks; a query that does not settle within RTRIES gathers is listed for the
+// streaming search as before.  Every lane takes part in every cross-lane step
+// (a finished or empty group only masks its own work).
+// k = n_i - 1 up to GROUP_KMAX<cap>: survivors aimed at 1.3 (k + 1) well below the cap
+template <int CAP>
+constexpr int GROUP_KMAX = CAP == 32 ? 16 : 40;
+
+template <int QW, int SPL>
+__global__ __launch_bounds__(256) void k_knn_radius_group(const GridParams* __restrict__ gpp,
+                                                          const int* __restrict__ cell_start,
+                                                          const int* __restrict__ sorted_id,
+                                                          const double* __restrict__ sx, int64_t N, int d,
+                                                          const int64_t* __restrict__ offsets, int n_max,
+                                                          int32_t* __restrict__ idx, int* __restrict__ list,
+                                                          int* __restrict__ list_count) {
+    static_assert(QW == 16 || QW == 32, "a group holds the density rows (9) of a query");
+    static_assert(QW * SPL == 32 || QW * SPL == 64, "survivor caps of GROUP_KMAX");
+    constexpr int QPW = WAVE / QW;   // queries per wavefront
+    constexpr int PCAP = SPL * QW;   // survivors per query
+    __shared__ __attribute__((aligned(16))) double skey[4 * QPW][PCAP];
+    __shared__ __attribute__((aligned(16))) unsigned sid[4 * QPW][PCAP];
+    const GridParams g = *gpp;
+    const int lane = lane_id(), wv = threadIdx.x / WAVE;
+    const int sl = lane & (QW - 1), gb = lane - sl, hq = wv * QPW + lane / QW;
+    const int64_t q = (int64_t)blockIdx.x * (4 * QPW) + hq;
+    bool active = q < N;
+    int qid = 0;
+    int64_t off = 0, ni = 0;
+    if (active) {
+        qid = sorted_id[q];
+        off = offsets[qid];
+        ni = offsets[qid + 1] - off;
+        if (ni < 1 || ni > n_max || ni > N) {
+            for (int64_t e = sl; e < ni; e += QW) idx[off + e] = -1;
+            active = false;
+        } else {
+            if (sl == 0) idx[off] = qid;
+            if (ni == 1) active = false;
+        }
+    }
+    const int k = (int)ni - 1;
+    double qx[3] = {0.0, 0.0, 0.0};
+    if (active) {
+        qx[0] = sx[q];
+        qx[1] = sx[N + q];
+        qx[2] = (d == 3) ? sx[2 * N + q] : 0.0;
+    }
+    int qc[3] = {0, 0, 0};
+    for (int a = 0; a < d; ++a) qc[a] = cell_coord(qx[a], g.origin[a], g.inv_cell, g.dims[a]);
+
+    // local density around the query's cell, as in k_knn_radius
+    double tau;
+    {
+        const int nrow = (d == 3) ? 9 : 3;
+        int cnt = 0, cells = 0;
+        if (active && sl < nrow) {
+            const int cy = qc[1] + sl % 3 - 1, cz = (d == 3) ? qc[2] + sl / 3 - 1 : 0;
+            if (cy >= 0 && cy < g.dims[1] && cz >= 0 && cz < g.dims[2]) {
+                const int xlo = max(qc[0] - 1, 0), xhi = min(qc[0] + 1, g.dims[0] - 1);
+                cnt = cell_start[lin3(g, xhi, cy, cz) + 1] - cell_start[lin3(g, xlo, cy, cz)];
+                cells = xhi - xlo + 1;
+            }
+        }
+        const int span = (d == 3) ? 16 : 4;  // lanes holding the rows
+        for (int o = 1; o < span; o <<= 1) {
+            cnt += __shfl_xor(cnt, o);
+            cells += __shfl_xor(cells, o);
+        }
+        cnt = __shfl(cnt, gb);
+        cells = __shfl(cells, gb);
+        // expected nodes within r: cnt / (cells c^d) V_d r^d; aim at about 1.3 (k + 1)
+        const double vol = (double)max(cells, 1) * ((d == 3) ? g.cell * g.cell * g.cell : g.cell * g.cell);
+        const double unit = (d == 3) ? 4.18879020478639098 : 3.14159265358979324;
+        const double v = 1.3 * (k + 1) * vol / ((double)max(cnt, 1) * unit);
+        const double r = (d == 3) ? cbrt(v) : sqrt(v);
+        tau = r * r;
+    }
+
+    int count = 0;
+    bool ok = !active;  // nothing to search
+    for (int attempt = 0; attempt < RTRIES; ++attempt) {
+        if (ballot64(!ok) == 0) break;
+        const bool work = !ok;
+        const double rho = sqrt(tau) * (1.0 + 1e-9);
+        const int ylo = cell_coord(qx[1] - rho, g.origin[1], g.inv_cell, g.dims[1]);
+        const int yhi = cell_coord(qx[1] + rho, g.origin[1], g.inv_cell, g.dims[1]);
+        const int zlo = (d == 3) ? cell_coord(qx[2] - rho, g.origin[2], g.inv_cell, g.dims[2]) : 0;
+        const int zhi = (d == 3) ? cell_coord(qx[2] + rho, g.origin[2], g.inv_cell, g.dims[2]) : 0;
+        const int ny = yhi - ylo + 1;
+        const int nrows = work ? ny * (zhi - zlo + 1) : 0;
+        int rmax = nrows;
+#pragma unroll
+        for (int o = QW; o < WAVE; o <<= 1) rmax = max(rmax, __shfl_xor(rmax, o));
+        if (work) count = 0;
+        for (int r0 = 0; r0 < rmax; r0 += QW) {
+            int st, ln;
+            radius_row(g, cell_start, d, qx, rho, ylo, zlo, ny, r0 + sl, nrows, st, ln);
+            int incl = ln;
+#pragma unroll
+            for (int o = 1; o < QW; o <<= 1) {
+                const int t = __shfl_up(incl, o, QW);
+                if (sl >= o) incl += t;
+            }
+            const int total = __shfl(incl, gb + QW - 1);
+            const int excl = incl - ln;
+            int tmax = total;
+#pragma unroll
+            for (int o = QW; o < WAVE; o <<= 1) tmax = max(tmax, __shfl_xor(tmax, o));
+            for (int base = 0; base < tmax; base += QW) {
+                const int e = base + sl;
+                // smallest row r of this group with incl[r] > e
+                int r = 0;
+#pragma unroll
+                for (int step = QW / 2; step > 0; step >>= 1) {
+                    const int v = __shfl(incl, gb + r + step - 1);
+                    if (v <= e) r += step;
+                }
+                const int sr = __shfl(st, gb + r);
+                const int er = __shfl(excl, gb + r);
+                const bool valid = e < total;
+                const int pos = valid ? sr + (e - er) : 0;
+                const unsigned cid = (unsigned)sorted_id[pos];
+                const double key = sq_key(qx, sx[pos], sx[N + pos], (d == 3) ? sx[2 * N + pos] : 0.0, d);
+                const bool pass = valid && cid != (unsigned)qid && key <= tau;
+                const unsigned hb = (unsigned)(ballot64(pass) >> gb) & (unsigned)((1ull << QW) - 1);
+                const int slot = count + __builtin_popcount(hb & ((1u << sl) - 1u));
+                if (pass && slot < PCAP) {
+                    skey[hq][slot] = key;
+                    sid[hq][slot] = cid;
+                }
+                count += __builtin_popcount(hb);
+            }
+        }
+        if (work) {
+            if (count >= k && count <= PCAP) {
+                ok = true;
+            } else {
+                const double ratio = 1.25 * k / (double)max(count, 1);
+                const double cr = cbrt(ratio);
+                double f = (count == 0) ? 4.0 : ((d == 3) ? cr * cr : ratio);
+                f = (count < k) ? fmax(f, 1.2) : fmin(f, 0.9);
+                tau *= f;
+            }
+        }
+    }
+    wave_lds_sync();
+    if (!active) return;
+    if (!ok) {  // left to the streaming search (k_knn_list)
+        if (sl == 0) list[atomicAdd(list_count, 1)] = (int)q;
+        return;
+    }
+    // count <= PCAP: each survivor counts the survivors before it on (key,
+    // index); the k smallest ranks are the stencil in order
+    double kl[SPL];
+    unsigned il[SPL];
+    int rank[SPL];
+#pragma unroll
+    for (int t = 0; t < SPL; ++t) {
+        const bool have = sl + QW * t < count;
+        kl[t] = have ? skey[hq][sl + QW * t] : 0.0;
+        il[t] = have ? sid[hq][sl + QW * t] : 0u;
+        rank[t] = 0;
+    }
+    for (int j = 0; j < count; j += 2) {  // slot count, read when count is odd, is in the buffer and not counted
+        const double2 kk = *reinterpret_cast<const double2*>(&skey[hq][j]);
+        const uint2 ii = *reinterpret_cast<const uint2*>(&sid[hq][j]);
+#pragma unroll
+        for (int t = 0; t < SPL; ++t) {
+            rank[t] += (kk.x < kl[t] || (kk.x == kl[t] && ii.x < il[t])) ? 1 : 0;
+            rank[t] += (j + 1 < count && (kk.y < kl[t] || (kk.y == kl[t] && ii.y < il[t]))) ? 1 : 0;
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < SPL; ++t)
+        if (sl + QW * t < count && rank[t] < k) idx[off + 1 + rank[t]] = (int32_t)il[t];
+}
+
 struct SelWorkspace {
     size_t gp, part, count, bsum, cell_of, rank, sorted_id, sx, list, total;
     int64_t cap;
@@ -821,9 +1004,22 @@ static rbf_status select_enqueue(rbf_ctx* ctx, const double* X, int64_t N, int d
     hipLaunchKernelGGL(k_bin_scatter, dim3(nbN), dim3(256), 0, s, X, N, d, count, cell_of, rank, sorted_id, sx);
     int64_t waves = N;
     dim3 grid((unsigned)((waves * WAVE + 255) / 256));
-    if (n_max - 1 <= RADIUS_KMAX) {
+    // four queries per wavefront (16 lanes each) where the survivors fit 2 or 4
+    // slots per lane; two (32 lanes, 2 slots) for the larger 2D stencils
+    if (n_max - 1 <= GROUP_KMAX<32> && d == 2) {
+        hipLaunchKernelGGL((k_knn_radius_group<16, 2>), dim3((unsigned)((N + 15) / 16)), dim3(256), 0, s, gp, count,
+                           sorted_id, sx, N, d, offsets, n_max, idx, list, list_count);
+    } else if (n_max - 1 <= GROUP_KMAX<64> && d == 3) {
+        hipLaunchKernelGGL((k_knn_radius_group<16, 4>), dim3((unsigned)((N + 15) / 16)), dim3(256), 0, s, gp, count,
+                           sorted_id, sx, N, d, offsets, n_max, idx, list, list_count);
+    } else if (n_max - 1 <= GROUP_KMAX<64>) {
+        hipLaunchKernelGGL((k_knn_radius_group<32, 2>), dim3((unsigned)((N + 7) / 8)), dim3(256), 0, s, gp, count,
+                           sorted_id, sx, N, d, offsets, n_max, idx, list, list_count);
+    } else if (n_max - 1 <= RADIUS_KMAX) {
         hipLaunchKernelGGL(k_knn_radius, grid, dim3(256), 0, s, gp, count, sorted_id, sx, N, d, offsets, n_max, idx,
                            (double)INFINITY, list, list_count);
+    }
+    if (n_max - 1 <= RADIUS_KMAX) {
         const unsigned lg = (unsigned)std::min<int64_t>((N + 3) / 4, 2048);  // persistent: at most 8k waves
         hipLaunchKernelGGL(k_knn_list, dim3(lg), dim3(256), 0, s, gp, count, sorted_id, sx, N, d, offsets, n_max,
                            idx, (double)INFINITY, list, list_count);
@@ -856,9 +1052,6 @@ extern "C" rbf_status rbf_select_stencils(rbf_ctx* ctx, const double* X, int64_t
 }
 
 // ------------------------------------------------------ cell order of a node set
-// Ascending node ids inside every cell (the atomic ranks of the binning give an
-// arbitrary order): one thread per cell, insertion sort; cells above 256 nodes
-// (degenerate clusters) keep their order.
 // Ascending ids inside each cell, whatever its size: the id at position p of
 // the cell-ordered array moves to the cell's start plus the number of ids of
 // its cell that are smaller (ids are distinct, so the ranks are a permutation of

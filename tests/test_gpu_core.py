@@ -47,11 +47,24 @@ def run_knn(X, sizes, dev, n_max=None):
 
 
 # ------------------------------------------------------------------ stencils
-@pytest.mark.parametrize("case", ["disk15", "cube35", "lshape_var", "torus20", "mixed_var129"])
+@pytest.mark.parametrize("case", ["disk15", "cube35", "lshape_var", "torus20", "mixed_var129", "disk_var17",
+                                  "cube10", "clustered2d", "disk_var41"])
 def test_knn_bit_exact(gpu, case):
     print(f"[knn] {case}", flush=True)
     if case == "disk15":
         X, sizes = ns.disk(0.0404, 1001).X, 15
+    elif case == "disk_var17":    # four queries per wavefront, sizes 1..17 mixed within a wavefront
+        nd = ns.disk(0.03, 11)
+        X, sizes = nd.X, np.random.default_rng(12).integers(1, 18, size=nd.N)
+    elif case == "disk_var41":    # two queries per wavefront (2D, up to 41 nodes)
+        nd = ns.disk(0.03, 15)
+        X, sizes = nd.X, np.random.default_rng(16).integers(17, 42, size=nd.N)
+    elif case == "cube10":        # four queries per wavefront in 3D
+        X, sizes = ns.cube_minus_sphere(1.0 / 20, 13).X, 10
+    elif case == "clustered2d":   # a dense cluster in a sparse set: radius estimates that miss, retries
+        rng = np.random.default_rng(14)
+        X = np.concatenate([rng.random((3000, 2)), 0.5 + 1e-3 * rng.standard_normal((600, 2))])
+        sizes = 15
     elif case == "cube35":
         X, sizes = ns.cube_minus_sphere(1.0 / 24, 1002).X, 35
     elif case == "lshape_var":
@@ -97,6 +110,21 @@ def test_knn_full_size_cube_sphere_sampled(gpu):
         k = oknn.sq_key(nd.X, i, allj)
         k[i] = np.inf
         order = np.lexsort((allj, k))[:34]
+        assert idx[off[i]] == i
+        assert np.array_equal(idx[off[i] + 1:off[i + 1]], order), i
+
+
+def test_knn_full_size_disk_sampled(gpu):
+    """1.7M-node unit disk, n=15 (the surrogate workload; four queries per wavefront): sampled nodes vs brute force."""
+    nd = ns.disk(ns.DISK_H / 30.0, 1001)
+    off, idx, *_ = run_knn(nd.X, 15, gpu)
+    rng = np.random.default_rng(1)
+    sample = np.concatenate([rng.choice(nd.N, 150, replace=False), np.nonzero(nd.is_boundary)[0][::500]])
+    allj = np.arange(nd.N)
+    for i in sample:
+        k = oknn.sq_key(nd.X, i, allj)
+        k[i] = np.inf
+        order = np.lexsort((allj, k))[:14]
         assert idx[off[i]] == i
         assert np.array_equal(idx[off[i] + 1:off[i + 1]], order), i
 
