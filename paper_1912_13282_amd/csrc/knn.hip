@@ -1020,7 +1020,9 @@ static rbf_status select_enqueue(rbf_ctx* ctx, const double* X, int64_t N, int d
                            (double)INFINITY, list, list_count);
     }
     if (n_max - 1 <= RADIUS_KMAX) {
-        const unsigned lg = (unsigned)std::min<int64_t>((N + 3) / 4, 2048);  // persistent: at most 8k waves
+        // persistent, 2k waves: the list is usually empty or short, and an idle
+        // launch of 2k blocks costs more than the few listed queries gain
+        const unsigned lg = (unsigned)std::min<int64_t>((N + 3) / 4, 512);
         hipLaunchKernelGGL(k_knn_list, dim3(lg), dim3(256), 0, s, gp, count, sorted_id, sx, N, d, offsets, n_max,
                            idx, (double)INFINITY, list, list_count);
     } else
