@@ -414,8 +414,11 @@ __device__ __forceinline__ void knn_stream(const GridParams& g, const int* __res
     qx[0] = sx[q];
     qx[1] = sx[N + q];
     qx[2] = (d == 3) ? sx[2 * N + q] : 0.0;
-    int qc[3] = {0, 0, 0};
-    for (int a = 0; a < d; ++a) qc[a] = cell_coord(qx[a], g.origin[a], g.inv_cell, g.dims[a]);
+    // the axes written out: an index over the runtime d would place g in scratch memory
+    int qc[3];
+    qc[0] = cell_coord(qx[0], g.origin[0], g.inv_cell, g.dims[0]);
+    qc[1] = cell_coord(qx[1], g.origin[1], g.inv_cell, g.dims[1]);
+    qc[2] = (d == 3) ? cell_coord(qx[2], g.origin[2], g.inv_cell, g.dims[2]) : 0;
 
     double TK[T];
     unsigned TI[T];
@@ -608,8 +611,11 @@ __global__ __launch_bounds__(256) void k_knn_radius(const GridParams* __restrict
     qx[0] = sx[q];
     qx[1] = sx[N + q];
     qx[2] = (d == 3) ? sx[2 * N + q] : 0.0;
-    int qc[3] = {0, 0, 0};
-    for (int a = 0; a < d; ++a) qc[a] = cell_coord(qx[a], g.origin[a], g.inv_cell, g.dims[a]);
+    // the axes written out: an index over the runtime d would place g in scratch memory
+    int qc[3];
+    qc[0] = cell_coord(qx[0], g.origin[0], g.inv_cell, g.dims[0]);
+    qc[1] = cell_coord(qx[1], g.origin[1], g.inv_cell, g.dims[1]);
+    qc[2] = (d == 3) ? cell_coord(qx[2], g.origin[2], g.inv_cell, g.dims[2]) : 0;
 
     // local density: nodes in the 3 x 3 (x 3) cells around the query (in the grid)
     double tau;
@@ -798,8 +804,11 @@ __global__ __launch_bounds__(256) void k_knn_radius_group(const GridParams* __re
         qx[1] = sx[N + q];
         qx[2] = (d == 3) ? sx[2 * N + q] : 0.0;
     }
-    int qc[3] = {0, 0, 0};
-    for (int a = 0; a < d; ++a) qc[a] = cell_coord(qx[a], g.origin[a], g.inv_cell, g.dims[a]);
+    // the axes written out: an index over the runtime d would place g in scratch memory
+    int qc[3];
+    qc[0] = cell_coord(qx[0], g.origin[0], g.inv_cell, g.dims[0]);
+    qc[1] = cell_coord(qx[1], g.origin[1], g.inv_cell, g.dims[1]);
+    qc[2] = (d == 3) ? cell_coord(qx[2], g.origin[2], g.inv_cell, g.dims[2]) : 0;
 
     // local density around the query's cell, as in k_knn_radius
     double tau;
