@@ -405,7 +405,7 @@ typedef struct rbf_solve_info {
  * context stream every 16 iterations and on return, when *info (host memory,
  * may be NULL) is filled.  Deterministic: every dot product is reduced in a
  * fixed order.  Workspace: rbf_bicgstab_workspace for the same N, nnz and
- * preconditioner (9 N + 10,240 float64 values and 256 bytes; block-Jacobi adds
+ * preconditioner (9 N + 5,120 float64 values and 256 bytes; block-Jacobi adds
  * the copy of M, about 12 (nnz + N) + 24 N bytes).
  * ------------------------------------------------------------------------ */
 rbf_status rbf_bicgstab_workspace(int64_t N, int64_t nnz, int precond, size_t* bytes);

@@ -93,8 +93,8 @@ __global__ __launch_bounds__(256) void k_assemble(int64_t N, int d, const int64_
 
 // ------------------------------------------------------------------ solver
 constexpr int RUNNING = -1;
-constexpr int NBMAX = 2048;      // blocks of the row-product kernels (bounds the block sums)
-constexpr int NBVEC = 2048;      // blocks of the vector kernels
+constexpr int NBMAX = 1024;      // blocks of the row-product kernels (bounds the block sums)
+constexpr int NBVEC = 1024;      // blocks of the vector kernels
 static_assert(NBVEC <= NBMAX, "the vector kernels share the block sums of the row products");
 constexpr int CHECK_EVERY = 16;  // iterations between host checks
 

@@ -169,7 +169,7 @@ def test_more_host_argument_errors_without_gpu(lib_path):
     assert L.rbf_bicgstab_workspace(I64(1000), I64(-1), 1, ctypes.byref(b)) == -1
     assert L.rbf_bicgstab_workspace(I64(1000), I64(9000), 7, ctypes.byref(b)) == -1
     assert L.rbf_bicgstab_workspace(I64(1000), I64(9000), 1, ctypes.byref(b)) == 0
-    assert b.value >= 9 * 1000 * 8 + 10240 * 8
+    assert b.value >= 9 * 1000 * 8 + 5120 * 8
     jac = b.value
     assert L.rbf_bicgstab_workspace(I64(1000), I64(9000), 2, ctypes.byref(b)) == 0
     assert b.value >= jac + 12 * (9000 + 1000) + 24 * 1000
