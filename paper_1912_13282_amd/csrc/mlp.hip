@@ -51,18 +51,23 @@ typedef __bf16 bf16x8 __attribute__((__vector_size__(8 * sizeof(__bf16))));
 typedef unsigned short u16x8 __attribute__((__vector_size__(8 * sizeof(unsigned short))));
 typedef float f32x4 __attribute__((__vector_size__(4 * sizeof(float))));
 
-// float -> bfloat16 bits, round to nearest, ties to even (finite inputs)
-__host__ __device__ __forceinline__ unsigned short bf16_bits(float x) {
-    unsigned u = __builtin_bit_cast(unsigned, x);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (unsigned short)(u >> 16);
+// float -> bfloat16 bits, round to nearest, ties to even: the conversion
+// instruction of gfx950 (two values per instruction; four integer operations
+// per value by hand were an eighth of the surrogate's VALU work)
+__device__ __forceinline__ unsigned short bf16_bits(float x) { return __builtin_bit_cast(unsigned short, (__bf16)x); }
+
+// two values into one 32-bit word (lo in the low half), the unit the conversion
+// writes: whole words keep the packed operands out of 16-bit inserts
+typedef unsigned u32x4 __attribute__((__vector_size__(4 * sizeof(unsigned))));
+__device__ __forceinline__ unsigned bf16x2_bits(float lo, float hi) {
+    return (unsigned)bf16_bits(lo) | ((unsigned)bf16_bits(hi) << 16);
 }
 
 __device__ __forceinline__ bf16x8 pack8(const float v[8]) {
-    u16x8 u;
+    u32x4 w;
 #pragma unroll
-    for (int j = 0; j < 8; ++j) u[j] = bf16_bits(v[j]);
-    return __builtin_bit_cast(bf16x8, u);
+    for (int j = 0; j < 4; ++j) w[j] = bf16x2_bits(v[2 * j], v[2 * j + 1]);
+    return __builtin_bit_cast(bf16x8, w);
 }
 
 __device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c) {
@@ -148,7 +153,7 @@ __device__ __forceinline__ void hidden_layer(const bf16x8* tiles, const float* _
                                              const bf16x8 (&in)[KB][NCT], bf16x8 (&out)[4][NCT],
                                              f32x4 (&gp)[8][NCT]) {
     const int lane = lane_id(), g = lane >> 4;
-    u16x8 ou[4][NCT];
+    u32x4 ow[4][NCT];
 #pragma unroll
     for (int ot = 0; ot < 8; ++ot) {
         f32x4 acc[NCT];
@@ -160,22 +165,25 @@ __device__ __forceinline__ void hidden_layer(const bf16x8* tiles, const float* _
 #pragma unroll
             for (int ct = 0; ct < NCT; ++ct) acc[ct] = mfma(a, in[kb][ct], acc[ct]);
         }
+        float b[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const float b = bias[16 * ot + 4 * g + r];
+        for (int r = 0; r < 4; ++r) b[r] = bias[16 * ot + 4 * g + r];
 #pragma unroll
-            for (int ct = 0; ct < NCT; ++ct) {
-                const float z = acc[ct][r] + b;
-                float gz;
+        for (int ct = 0; ct < NCT; ++ct) {
+            float gz[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float z = acc[ct][r] + b[r];
                 if constexpr (GRAD) {
                     float gpz;
-                    gelu_both(z, gz, gpz);
+                    gelu_both(z, gz[r], gpz);
                     gp[ot][ct][r] = gpz;
                 } else {
-                    gz = gelu(z);
+                    gz[r] = gelu(z);
                 }
-                ou[ot >> 1][ct][(ot & 1) * 4 + r] = bf16_bits(gz);
             }
+#pragma unroll
+            for (int h = 0; h < 2; ++h) ow[ot >> 1][ct][(ot & 1) * 2 + h] = bf16x2_bits(gz[2 * h], gz[2 * h + 1]);
         }
         // keep each tile's operand loads next to their use (bounds register pressure)
         __builtin_amdgcn_sched_barrier(0);
@@ -183,7 +191,7 @@ __device__ __forceinline__ void hidden_layer(const bf16x8* tiles, const float* _
 #pragma unroll
     for (int kb = 0; kb < 4; ++kb)
 #pragma unroll
-        for (int ct = 0; ct < NCT; ++ct) out[kb][ct] = __builtin_bit_cast(bf16x8, ou[kb][ct]);
+        for (int ct = 0; ct < NCT; ++ct) out[kb][ct] = __builtin_bit_cast(bf16x8, ow[kb][ct]);
 }
 
 // Whole network for NCT column tiles; y[ct][r] = output 4g + r of sample 16 ct + (lane & 15)
@@ -324,20 +332,19 @@ template <int NOB>
 __device__ __forceinline__ void back_hidden(const bf16x8* __restrict__ tiles, const bf16x8 (&dzb)[NOB][1],
                                             const f32x4 (&gp)[8][1], f32x4 (&dz)[8], bf16x8 (&dzb_next)[4][1]) {
     const int lane = lane_id();
-    u16x8 ou[4];
+    u32x4 ow[4];
 #pragma unroll
     for (int kt = 0; kt < 8; ++kt) {
         f32x4 acc = zero4();
 #pragma unroll
         for (int ob = 0; ob < NOB; ++ob) acc = mfma(tiles[(kt * NOB + ob) * 64 + lane], dzb[ob][0], acc);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            dz[kt][r] = acc[r] * gp[kt][0][r];
-            ou[kt >> 1][(kt & 1) * 4 + r] = bf16_bits(dz[kt][r]);
-        }
+        for (int r = 0; r < 4; ++r) dz[kt][r] = acc[r] * gp[kt][0][r];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) ow[kt >> 1][(kt & 1) * 2 + h] = bf16x2_bits(dz[kt][2 * h], dz[kt][2 * h + 1]);
     }
 #pragma unroll
-    for (int kb = 0; kb < 4; ++kb) dzb_next[kb][0] = __builtin_bit_cast(bf16x8, ou[kb]);
+    for (int kb = 0; kb < 4; ++kb) dzb_next[kb][0] = __builtin_bit_cast(bf16x8, ow[kb]);
 }
 
 // Partial gradients of one block of 64 samples (rows sel[b] of x and t, or b).
