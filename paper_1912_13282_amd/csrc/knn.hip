@@ -51,36 +51,58 @@ __global__ __launch_bounds__(256) void k_zero_ints(int* __restrict__ p, int64_t 
     if (i < n) p[i] = 0;
 }
 
-__global__ __launch_bounds__(256) void k_bbox_partial(const double* __restrict__ X, int64_t N, int d,
+// Bounding-box partials of the nodes (grid-stride, four nodes per thread and
+// pass so their loads are in flight together; an index clamped into range
+// repeats a node, which leaves a minimum or maximum unchanged).
+template <int D>
+__global__ __launch_bounds__(256) void k_bbox_partial(const double* __restrict__ X, int64_t N,
                                                       double* __restrict__ part) {
     __shared__ double sm[4][6];
     double mn[3] = {INFINITY, INFINITY, INFINITY};
     double mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        for (int a = 0; a < d; ++a) {
-            double v = X[i * d + a];
-            mn[a] = fmin(mn[a], v);
-            mx[a] = fmax(mx[a], v);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < N; i0 += 4 * stride) {
+        double v[4][D];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t i = min(i0 + u * stride, N - 1);
+#pragma unroll
+            for (int a = 0; a < D; ++a) v[u][a] = X[i * D + a];
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                mn[a] = fmin(mn[a], v[u][a]);
+                mx[a] = fmax(mx[a], v[u][a]);
+            }
     }
+#pragma unroll
     for (int a = 0; a < 3; ++a) {
         mn[a] = wave_min_d(mn[a]);
         mx[a] = wave_max_d(mx[a]);
     }
-    int w = threadIdx.x / WAVE;
+    const int w = threadIdx.x / WAVE;
     if (lane_id() == 0)
+#pragma unroll
         for (int a = 0; a < 3; ++a) {
             sm[w][a] = mn[a];
             sm[w][3 + a] = mx[a];
         }
     __syncthreads();
     if (threadIdx.x < 6) {
-        int a = threadIdx.x;
+        const int a = threadIdx.x;
         double v = sm[0][a];
         for (int k = 1; k < 4; ++k) v = (a < 3) ? fmin(v, sm[k][a]) : fmax(v, sm[k][a]);
         part[blockIdx.x * 6 + a] = v;
     }
+}
+
+inline void bbox_enqueue(hipStream_t s, int nbb, const double* X, int64_t N, int d, double* part) {
+    if (d == 3)
+        hipLaunchKernelGGL(k_bbox_partial<3>, dim3(nbb), dim3(256), 0, s, X, N, part);
+    else
+        hipLaunchKernelGGL(k_bbox_partial<2>, dim3(nbb), dim3(256), 0, s, X, N, part);
 }
 
 __global__ __launch_bounds__(64) void k_grid_setup(const double* __restrict__ part, int nb, int64_t N, int d,
@@ -997,7 +1019,7 @@ static rbf_status select_enqueue(rbf_ctx* ctx, const double* X, int64_t N, int d
     const double target = fmax(1.0, ((d == 3) ? CELL_FILL_3D : CELL_FILL_2D) * (double)n_max / unit_ball);
 
     int nbb = (int)std::min<int64_t>(BBOX_BLOCKS, (N + 255) / 256);
-    hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(256), 0, s, X, N, d, part);
+    bbox_enqueue(s, nbb, X, N, d, part);
     hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(64), 0, s, part, nbb, N, d, target, L.cap, gp);
     // cleared by a kernel (a memset node in a captured graph is not reliable);
     // count[cap + 1] is the length of the radius search's fallback list
@@ -1102,7 +1124,7 @@ hipError_t cell_order_enqueue(hipStream_t s, const double* X, int64_t N, int d, 
     int* rank = (int*)(w + L.rank);
     double* sx = (double*)(w + L.sx);
     const int nbb = (int)std::min<int64_t>(BBOX_BLOCKS, (N + 255) / 256);
-    hipLaunchKernelGGL(k_bbox_partial, dim3(nbb), dim3(256), 0, s, X, N, d, part);
+    bbox_enqueue(s, nbb, X, N, d, part);
     hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(64), 0, s, part, nbb, N, d, fmax(1.0, per_cell), L.cap, gp);
     hipLaunchKernelGGL(k_zero_ints, dim3((unsigned)((L.cap + 2 + 255) / 256)), dim3(256), 0, s, count,
                        (int64_t)L.cap + 2);
