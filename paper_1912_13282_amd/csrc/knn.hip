@@ -561,8 +561,11 @@ __global__ __launch_bounds__(256) void k_knn_list(const GridParams* __restrict__
                                                   int64_t N, int d, const int64_t* __restrict__ offsets, int n_max,
                                                   int32_t* __restrict__ idx, double key_inf,
                                                   const int* __restrict__ list, const int* __restrict__ list_count) {
-    const GridParams g = *gpp;
+    // the list length first: the grid parameters are copied into per-thread
+    // storage (they are indexed by axis), which an idle launch should not pay for
     const int nl = __builtin_amdgcn_readfirstlane(*list_count);
+    if ((int)(blockIdx.x * (blockDim.x / WAVE)) >= nl) return;  // uniform: nothing listed for this block
+    const GridParams g = *gpp;
     const int nw = (int)(gridDim.x * (blockDim.x / WAVE));
     for (int i = (int)(blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE); i < nl; i += nw)
         knn_stream_query<1>(g, cell_start, sorted_id, sx, N, d, offsets, n_max, idx, key_inf,
