@@ -256,6 +256,31 @@ def test_bicgstab_csr_with_ragged_rows(gpu, precond):
     assert np.abs(xh - ud).max() <= 1e5 * 10 * tol * np.abs(ud).max()
 
 
+
+@pytest.mark.parametrize("precond", ["jacobi", "block_jacobi"])
+def test_bicgstab_restarts_from_a_drifted_residual(gpu, precond):
+    """A start 1e8 times too large: the recursively updated residual drifts from
+    b - M x by the rounding of the first, huge residuals (about 1e-8 of |b|), far above
+    the 1e-12 tolerance.  The check of the converged x must restart from it and end
+    with the recomputed residual within 2 tol."""
+    rb = _rb()
+    nd, kind, normals, off, idx, W, f, g, u0 = _annulus_problem(0.12, d=3, n=35, P=3, neumann=False)
+    vals, rhs = implicit.assemble(off, idx, W[0], W[1:], kind, normals, f=f, g=g)
+    ud = implicit.solve(off, idx, vals, rhs)
+    tol = 1e-12
+    n_max = int(np.diff(off).max())
+    x0 = 1e8 * np.random.default_rng(3).standard_normal(nd.N)
+    pc = rb.block_jacobi(_t(nd.X, gpu), _t(off, gpu), _t(idx, gpu), _t(vals, gpu)) if precond == "block_jacobi" \
+        else None
+    x, info = rb.bicgstab(_t(off, gpu), _t(idx, gpu), _t(vals, gpu), n_max, _t(rhs, gpu), x=_t(x0, gpu), tol=tol,
+                          max_iter=20000, precond=precond, pc=pc)
+    assert info["status"] == rb.SOLVE_CONVERGED, info
+    xh = x.cpu().numpy()
+    res = _scaled_residual(off, idx, vals, rhs, xh, jacobi=precond == "jacobi")
+    assert res <= 2.5 * tol, (res, info)
+    assert np.abs(xh - ud).max() <= 1e5 * 10 * tol * np.abs(ud).max(), np.abs(xh - ud).max()
+
+
 @pytest.mark.parametrize("precond", ["jacobi", "block_jacobi"])
 def test_bicgstab_outcomes(gpu, precond):
     rb = _rb()
