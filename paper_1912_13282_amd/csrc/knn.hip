@@ -156,16 +156,42 @@ __device__ __forceinline__ int cell_coord(double x, double o, double inv, int di
     return c < 0 ? 0 : (c >= dim ? dim - 1 : c);
 }
 
+// Rank of this lane's node among the nodes of its cell: the lanes of the
+// wavefront holding the same cell take consecutive ranks from one atomic
+// increment by the lowest of them.  The count is bound by the number of
+// increments; nodes that follow each other in the input often share a cell
+// (2D disk: 78 to 57 us; the 3D sets, about one node per cell along a run of
+// the input, are unchanged).  Lanes that are not active take no part.
+__device__ __forceinline__ int wave_cell_rank(int* __restrict__ count, int lin) {
+    const int lane = lane_id();
+    uint64_t todo = ballot64(true);
+    int leader = lane, within = 0, n_same = 0;
+    while (todo) {  // uniform: one pass per distinct cell of the wavefront
+        const int L = first_lane(todo);
+        const int c = __builtin_amdgcn_readlane(lin, L);
+        const uint64_t same = ballot64(lin == c) & todo;
+        if ((same >> lane) & 1ull) {
+            leader = L;
+            within = __builtin_popcountll(same & ((1ull << lane) - 1ull));
+        }
+        if (lane == L) n_same = __builtin_popcountll(same);
+        todo &= ~same;
+    }
+    int base = 0;
+    if (leader == lane) base = atomicAdd(&count[lin], n_same);
+    return __shfl(base, leader) + within;
+}
+
 __global__ __launch_bounds__(256) void k_bin_count(const double* __restrict__ X, int64_t N, int d,
                                                    const GridParams* __restrict__ gp, int* __restrict__ count,
                                                    int* __restrict__ cell_of, int* __restrict__ rank) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= N) return;
+    if (i >= N) return;  // the rank below is taken over the lanes still active
     int c[3] = {0, 0, 0};
     for (int a = 0; a < d; ++a) c[a] = cell_coord(X[i * d + a], gp->origin[a], gp->inv_cell, gp->dims[a]);
     int lin = c[0] + gp->dims[0] * (c[1] + gp->dims[1] * c[2]);
     cell_of[i] = lin;
-    rank[i] = atomicAdd(&count[lin], 1);
+    rank[i] = wave_cell_rank(count, lin);
 }
 
 // block-local exclusive scan of SCAN_CHUNK ints (256 threads x 4 each); returns the block total
